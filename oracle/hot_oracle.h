@@ -1,0 +1,78 @@
+/*
+ * hot_oracle.h -- FP64 CPU oracle for HOT (Halpern accelerating method for
+ * optimal transport, arXiv 2408.00598).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * package's smoke() check and the benchmark's CPU-baseline leg may load it.
+ * It shares no code, header, table or helper with the GPU library.
+ *
+ * Conventions follow the paper's standard-form LP (Sec. 2.1, eqs. standLP0,
+ * def:A1A2A3, Mat:A&b, def:A4), written 0-based:
+ *   grid m x n, M = m n, N = m^2 n + m n^2, M3 = 3M - 1;
+ *   x = [f1; f2],  f1_{i,k,j} at x[(j*m + k)*m + i],
+ *                  f2_{k,j,l} at x[m*m*n + (l*n + j)*m + k];
+ *   y = [y1; y2; y3], y1 row (j,k) at j*m+k (conservation at bin (k,j)),
+ *                     y2 row (j,i) at M + j*m+i (source marginal of bin (i,j)),
+ *                     y3 row (l,k) at 2M + l*m+k (target marginal of bin (k,l)),
+ *                     the row (l,k) = (n-1,m-1) is dropped (def:A4);
+ *   histograms are row-major images: mu[i*n + j] is the mass of bin (i,j).
+ */
+#ifndef HOT_ORACLE_H
+#define HOT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double tol;        /* stop when the relative KKT residual (eq. kkt_res) <= tol; <=0: never */
+  int32_t max_iter;  /* hard cap on iterations */
+  int32_t check_every; /* check cadence T (>=1) */
+  double sigma;      /* > 0: use it; <= 0: sigma = ||b|| / ||c|| */
+  int32_t restart;   /* 1: restart rule on, 0: Algorithm 2 verbatim */
+  int32_t fixed_iters; /* > 0: run exactly this many updates, no stop test */
+} or_params;
+
+typedef struct {
+  double primal_obj;   /* <c, xbar> */
+  double dual_obj;     /* <b, ybar> */
+  double kkt;          /* max of the three relative residuals */
+  double res_dual;     /* ||A^T ybar + zbar - c|| / (1 + ||c||) */
+  double res_comp;     /* ||min(xbar, zbar)|| / (1 + ||xbar|| + ||zbar||) */
+  double res_primal;   /* ||A xbar - b|| / (1 + ||b||) */
+  double sigma;
+  double fp_res;       /* ||s - shat|| with s = x/sigma + z: fixed-point residual */
+  int32_t iters;       /* number of updates performed */
+  int32_t restarts;
+  int32_t converged;
+} or_result;
+
+void or_dims(int32_t m, int32_t n, int64_t *N, int64_t *M3);
+void or_cost(int32_t m, int32_t n, double *c);
+void or_bvec(int32_t m, int32_t n, const double *mu1, const double *mu2, double *b);
+void or_A(int32_t m, int32_t n, const double *x, double *out);
+void or_AT(int32_t m, int32_t n, const double *y, double *out);
+void or_solve_aat(int32_t m, int32_t n, const double *R, double *y);
+void or_kkt(int32_t m, int32_t n, const double *mu1, const double *mu2,
+            const double *x, const double *y, const double *z, or_result *res);
+int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
+               const or_params *p, double *xbar, double *ybar, double *zbar,
+               double *s_state, or_result *res);
+int64_t or_recover(int32_t m, int32_t n, const double *x, int64_t cap,
+                   int32_t *src, int32_t *dst, double *mass);
+int64_t or_repair(int32_t m, int32_t n, const double *mu1, const double *mu2,
+                  int64_t nnz, int64_t cap, int32_t *src, int32_t *dst,
+                  double *mass);
+void or_marginals(int32_t m, int32_t n, int64_t nnz, const int32_t *src,
+                  const int32_t *dst, const double *mass, double *row,
+                  double *col);
+int32_t or_simplex(int32_t rows, int32_t cols, const double *A, const double *b,
+                   const double *c, double *x, double *obj);
+double or_w2_1d(int32_t n, const double *a, const double *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
