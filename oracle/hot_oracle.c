@@ -260,7 +260,10 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   double *R = (double *)malloc((size_t)M3 * sizeof(double));
   or_cost(m, n, c);
   or_bvec(m, n, mu1, mu2, b);
-  const double sigma = p->sigma > 0 ? p->sigma : nrm2(M3, b) / nrm2(N, c);
+  /* sigma = ||b||/||c||; on a 1 x 1 grid every cost is zero and the ratio is
+   * undefined, so sigma = 1 there. */
+  const double nb = nrm2(M3, b), nc = nrm2(N, c);
+  const double sigma = p->sigma > 0 ? p->sigma : ((nc > 0 && nb > 0) ? nb / nc : 1.0);
   const int32_t T = p->check_every > 0 ? p->check_every : 1;
   const int32_t fixed = p->fixed_iters > 0 ? p->fixed_iters : 0;
 
