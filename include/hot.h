@@ -1,0 +1,165 @@
+/*
+ * hot.h -- C ABI of libhot, an MI355X (gfx950) implementation of HOT, the
+ * Halpern accelerating method for optimal transport between two histograms
+ * on an m x n grid with squared Euclidean ground cost (arXiv 2408.00598).
+ *
+ * The library solves the reduced OT model (Sec. 2.1, eq. partite-graph /
+ * standLP) with Algorithm 2 (alg:HOT), the linear-time solve of Prop. 3
+ * (prop:linsol_OT) and the relative KKT stopping rule (eq. kkt_res), and
+ * recovers a transport plan with Algorithm 1 (alg:transportplan).
+ *
+ * Conventions shared by every entry point
+ *  - Histograms are caller-owned DEVICE buffers of m*n doubles, row-major:
+ *    mu[i*n + j] is the mass of bin (i, j).  They must be nonnegative,
+ *    finite, and have equal totals (the paper assumes total 1, Sec. 2.1).
+ *  - Flow and dual vectors exported by hot_solution_export use the paper's
+ *    vectorisation (def:A1A2A3): x = [f1; f2] with f1_{i,k,j} at
+ *    (j*m + k)*m + i and f2_{k,j,l} at m*m*n + (l*n + j)*m + k; y = [y1; y2;
+ *    y3] with y1 at j*m+k, y2 at m*n + j*m+i, y3 at 2*m*n + l*m+k (the row
+ *    (l,k) = (n-1, m-1) is removed, def:A4), 3*m*n - 1 entries in total.
+ *  - Every function returns a status; nothing aborts or throws across the
+ *    ABI.  On error, output buffers are left unspecified unless stated.
+ *  - Streams: work is enqueued on the given hipStream_t (0 = null stream).
+ *    Synchronous calls (hot_solve, hot_recover_plan) return when done.
+ *  - One context may be used by one host thread at a time (an internal mutex
+ *    serialises concurrent calls on the same context).
+ */
+#ifndef HOT_H
+#define HOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hot_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+  HOT_OK = 0,
+  HOT_E_INVALID = 1,       /* bad argument or histogram (see hot_problem) */
+  HOT_E_NOMEM = 2,         /* device allocation failed / budget exceeded */
+  HOT_E_DEVICE = 3,        /* HIP runtime error */
+  HOT_E_NOT_CONVERGED = 4, /* max_iter reached; result holds the last iterate */
+  HOT_E_BUSY = 5,          /* server full or handle still running */
+  HOT_E_CANCELLED = 6,
+  HOT_E_NUMERIC = 7        /* non-finite value appeared in the iteration */
+} hot_status;
+
+typedef enum {
+  HOT_FP64 = 0,        /* flow state stored and streamed in FP64 */
+  HOT_FP32_STREAM = 1  /* flow state stored in FP32; all reductions, the
+                          linear solve and per-element arithmetic in FP64 */
+} hot_precision;
+
+/* hot_problem.flags */
+#define HOT_FLAG_RESTART 0x1u     /* restart rule on (the default reading) */
+#define HOT_FLAG_FIXED_ITERS 0x2u /* run exactly max_iter updates of Alg. 2,
+                                     no stopping test, no restart; the result
+                                     is w_bar at the final iterate */
+
+typedef struct {
+  int32_t m, n;            /* grid rows, columns: 1 <= m, n <= 4096 */
+  const double *mu1;       /* device, m*n, source histogram */
+  const double *mu2;       /* device, m*n, target histogram */
+  double tol;              /* relative KKT tolerance (eq. kkt_res), > 0 */
+  int32_t max_iter;        /* iteration cap (>= 1) */
+  int32_t check_every;     /* KKT/restart check cadence T (>= 1; 10 typical) */
+  double sigma;            /* penalty sigma of Alg. 2; <= 0 selects ||b||/||c|| */
+  int32_t prec;            /* hot_precision */
+  uint32_t flags;          /* HOT_FLAG_* */
+} hot_problem;
+
+typedef struct {
+  double primal_obj;  /* <c, x_bar>: the reduced objective, = W2^2 at optimum */
+  double dual_obj;    /* <b, y_bar> */
+  double kkt;         /* max(res_primal, res_dual, res_comp), eq. kkt_res */
+  double res_primal;  /* ||A x_bar - b|| / (1 + ||b||) */
+  double res_dual;    /* ||A^T y_bar + z_bar - c|| / (1 + ||c||) */
+  double res_comp;    /* ||min(x_bar, z_bar)|| / (1 + ||x_bar|| + ||z_bar||) */
+  double sigma;       /* sigma used */
+  double seconds;     /* wall time of the solve on the host clock */
+  int32_t iters;      /* updates performed (Alg. 2 iterations) */
+  int32_t restarts;
+  int32_t status;     /* hot_status of this problem */
+  int32_t reserved;
+} hot_result;
+
+typedef struct hot_ctx hot_ctx;
+typedef struct hot_solution hot_solution;
+typedef struct hot_batch hot_batch;
+typedef struct hot_server hot_server;
+
+/* Create a context on HIP device `device`.  Owns the workspace pool.
+ * Returns HOT_E_DEVICE if the device cannot be used (e.g. no GPU). */
+hot_status hot_ctx_create(int device, hot_ctx **out);
+void hot_ctx_destroy(hot_ctx *ctx);
+
+/* Text of the last error recorded on ctx (never NULL; "" if none). */
+const char *hot_ctx_last_error(const hot_ctx *ctx);
+const char *hot_status_string(hot_status s);
+
+/* Device bytes one problem needs (state buffers, sums, dual vectors).
+ * Pure host arithmetic; 0 for invalid sizes. */
+size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags);
+
+/* Upper bound on the number of plan entries hot_recover_plan may write:
+ * m*n*(m+n-1) from Algorithm 1 plus 2*m*n - 1 from the marginal repair. */
+int64_t hot_plan_capacity(int32_t m, int32_t n);
+
+/* Solve one problem with Algorithm 2 (Steps 1-4, restart rule when
+ * HOT_FLAG_RESTART is set) until the relative KKT residual of w_bar is
+ * <= tol at a check, or max_iter.  Blocks until done.
+ * sol_out (nullable): receives a handle that keeps the final iterate on the
+ * device for hot_recover_plan / hot_solution_export; free it with
+ * hot_solution_free.  res (required) receives the result.
+ * Returns HOT_OK, HOT_E_NOT_CONVERGED (res filled with the last iterate),
+ * HOT_E_NUMERIC, HOT_E_INVALID (bad sizes, tol, negative/non-finite mass or
+ * totals differing by more than 1e-9 relative), HOT_E_NOMEM, HOT_E_DEVICE. */
+hot_status hot_solve(hot_ctx *ctx, const hot_problem *prob, hot_stream_t stream,
+                     hot_solution **sol_out, hot_result *res);
+
+/* Copy the final iterate of a solution into caller-owned DEVICE buffers in
+ * the paper's ordering (any pointer may be NULL to skip it):
+ * xbar, zbar: N = m*m*n + m*n*n doubles; ybar: 3*m*n - 1 doubles;
+ * s: the Halpern state x/sigma + z of the last update, N doubles. */
+hot_status hot_solution_export(hot_ctx *ctx, const hot_solution *sol,
+                               hot_stream_t stream, double *xbar, double *ybar,
+                               double *zbar, double *s);
+void hot_solution_free(hot_solution *sol);
+
+/* Algorithm 1 on the clipped flows max(x_bar, 0) of `sol`, followed by the
+ * marginal repair (rows above mu1 scaled down, then columns above mu2, then
+ * the remaining deficits coupled north-west-corner in bin order).  Writes
+ * entries (src bin i*n+j, dst bin k*n+l, mass) to caller-owned DEVICE arrays
+ * of `capacity` entries; capacity >= hot_plan_capacity(m, n) is required
+ * (HOT_E_INVALID otherwise).  *nnz receives the entry count.  marg_err
+ * (host, 4 doubles, nullable): L1 errors of row and column marginals before
+ * repair, then after repair.  Entries of bin (k,j) are contiguous, ordered
+ * by (k*n + j), then by source row i, then by target column l; the repair
+ * entries follow. */
+hot_status hot_recover_plan(hot_ctx *ctx, const hot_solution *sol,
+                            hot_stream_t stream, int32_t *src, int32_t *dst,
+                            double *mass, int64_t capacity, int64_t *nnz,
+                            double *marg_err);
+
+/* Solve A A^T y = R with the structured solve of Prop. 3 on the device.
+ * R, y: DEVICE buffers of 3*m*n - 1 doubles in the paper's row order. */
+hot_status hot_aat_solve(hot_ctx *ctx, int32_t m, int32_t n, const double *R,
+                         double *y, hot_stream_t stream);
+
+/* Batched solves: many problems (sizes may differ) share every launch; the
+ * iteration loop runs device-side in captured HIP graphs.  Submit returns
+ * once the work is enqueued and a host thread drives it; hot_batch_wait
+ * blocks, fills results[count] and frees the handle.  Each problem's result
+ * equals its hot_solve result (same kernels, same reduction order). */
+hot_status hot_batch_submit(hot_ctx *ctx, const hot_problem *probs,
+                            int32_t count, hot_stream_t stream,
+                            hot_batch **out);
+hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOT_H */

@@ -1,0 +1,738 @@
+// Host runtime and C ABI of libhot (see include/hot.h).
+//
+// A "Batch" holds one or more problems laid out back to back in shared
+// device buffers (flow state, sums, dual vectors, control blocks).  Every
+// iteration is one slab pass + one pair reduce + one pair solve over all
+// problems of the batch; the loop body is captured once into a HIP graph of
+// kGraphIters iterations and relaunched until every problem has stopped.
+// The stop / restart decisions are taken on the device, so the host only
+// polls a status word per problem between graph launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hot.h"
+#include "hot_internal.h"
+#include "hot_runtime.h"
+
+namespace hot {
+
+void launch_iteration(const LaunchArgs& a, int par, hipStream_t st);
+void launch_setup_mu(const double* mu1, const double* mu2, int m, int n, double* mu1T,
+                     double* mu2c, hipStream_t st);
+void launch_export(const LaunchArgs& a, int par, int pair, int64_t N, double* xbar,
+                   double* zbar, double* sout, hipStream_t st);
+void launch_export_y(const LaunchArgs& a, int pair, int64_t M3, double* y, hipStream_t st);
+void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
+                      hipStream_t st);
+void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
+                             double* out, hipStream_t st);
+
+static int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+static int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+static int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ||c||^2 of the reduced model: n copies of the m x m slab cost and m copies
+// of the n x n slab cost, each sum_{p,q} (p-q)^4.
+static double slab_cost_sq(int L) {
+  unsigned __int128 s = 0;
+  for (int d = 1; d < L; ++d) {
+    unsigned __int128 d4 = (unsigned __int128)d * d * d * d;
+    s += 2 * (unsigned __int128)(L - d) * d4;
+  }
+  return (double)s;
+}
+
+Tuning default_tuning() {
+  Tuning t;
+  t.item_elems = 65536;
+  t.rows_per_block = 8;
+  return t;
+}
+
+size_t Layout::bytes() const {
+  return (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
+         (size_t)cp_len * 8 * 2 + (size_t)items.size() * (kKI * 8 + sizeof(SlabItem)) +
+         (size_t)arr_len * 8 + (size_t)vec_len * 8 + geo.size() * sizeof(PairGeo) +
+         blocks.size() * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 + 4096;
+}
+
+bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
+                  Layout& lay, std::string& err) {
+  lay = Layout();
+  lay.fp32 = fp32;
+  lay.elem_size = fp32 ? 4 : 8;
+  const int W = fp32 ? 4 : 2;
+  int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0;
+  int maxvpl = 1;
+  for (size_t p = 0; p < shapes.size(); ++p) {
+    const int m = shapes[p].first, n = shapes[p].second;
+    if (m < 1 || n < 1 || m > kMaxSide || n > kMaxSide) {
+      err = "grid sides must be in [1, " + std::to_string(kMaxSide) + "]";
+      return false;
+    }
+    PairGeo g;
+    std::memset(&g, 0, sizeof(g));
+    g.m = m;
+    g.n = n;
+    g.item0 = (int32_t)lay.items.size();
+    for (int fam = 0; fam < 2; ++fam) {
+      FamGeo& F = g.f[fam];
+      F.L = fam == 0 ? m : n;
+      F.nslab = fam == 0 ? n : m;
+      F.P = (int32_t)round_up(F.L, W);
+      const int Q = F.P / W;
+      int LR, vpl;
+      if (Q <= 64) {
+        LR = next_pow2(Q);
+        vpl = 1;
+      } else {
+        LR = 64;
+        vpl = (Q + 63) / 64;
+      }
+      F.lrs = ilog2(LR);
+      F.vpl = vpl;
+      maxvpl = std::max(maxvpl, vpl);
+      const int step = 4 * (64 / LR);  // rows one workgroup covers per step
+      int rows = (int)std::max<int64_t>(1, tune.item_elems / F.P);
+      rows = (int)round_up(rows, step);
+      if (rows >= F.L) rows = F.L;
+      F.rpc = rows;
+      F.nchunk = (F.L + rows - 1) / rows;
+      soff = round_up(soff, 64);
+      F.soff = soff;
+      soff += (int64_t)F.nslab * F.L * F.P;
+      F.aboff = aboff;
+      aboff += (int64_t)F.nslab * 2 * F.L;
+      F.sumoff = aboff;
+      aboff += (int64_t)F.nslab * 2;
+      F.rsoff = rsoff;
+      rsoff += (int64_t)F.nslab * F.L;
+      F.cpoff = cpoff;
+      cpoff += (int64_t)F.nslab * F.nchunk * F.L;
+      for (int s = 0; s < F.nslab; ++s)
+        for (int c = 0; c < F.nchunk; ++c) lay.items.push_back(SlabItem{(int32_t)p, fam, s, c});
+    }
+    g.nitem = (int32_t)lay.items.size() - g.item0;
+    int nblk = std::max(1, (std::max(m, n) + tune.rows_per_block - 1) / tune.rows_per_block);
+    g.jpb = (n + nblk - 1) / nblk;
+    g.kpb = (m + nblk - 1) / nblk;
+    nblk = std::max((n + g.jpb - 1) / g.jpb, (m + g.kpb - 1) / g.kpb);
+    g.nblk = nblk;
+    g.ipb = (g.nitem + nblk - 1) / nblk;
+    g.blk0 = (int32_t)lay.blocks.size();
+    for (int b = 0; b < nblk; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b});
+    g.moff = moff;
+    moff += 5 * (int64_t)m * n;
+    g.voff = voff;
+    voff += vec_size(g);
+    g.norm_c = std::sqrt((double)n * slab_cost_sq(m) + (double)m * slab_cost_sq(n));
+    lay.geo.push_back(g);
+  }
+  lay.state_elems = round_up(std::max<int64_t>(soff, 64), 64);
+  lay.ab_len = std::max<int64_t>(aboff, 1);
+  lay.rs_len = std::max<int64_t>(rsoff, 1);
+  lay.cp_len = std::max<int64_t>(cpoff, 1);
+  lay.arr_len = std::max<int64_t>(moff, 1);
+  lay.vec_len = std::max<int64_t>(voff, 1);
+  lay.maxvpl = maxvpl;
+  return true;
+}
+
+}  // namespace hot
+
+using namespace hot;
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct hot_ctx {
+  int device = 0;
+  std::mutex mu;
+  std::string err;
+  Tuning tune = default_tuning();
+};
+
+#define HIPCK(expr)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      if (ctx) ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+      return HOT_E_DEVICE;                                                           \
+    }                                                                                \
+  } while (0)
+
+namespace hot {
+
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  graph_exec = nullptr;
+  graph = nullptr;
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+  if (host_ctl) (void)hipHostFree(host_ctl);
+  host_ctl = nullptr;
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+  stream = nullptr;
+}
+
+hot_status Workspace::alloc_all(hot_ctx* ctx) {
+  auto A = [&](void** p, size_t bytes) -> hot_status {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (ctx) ctx->err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+      return HOT_E_NOMEM;
+    }
+    allocs.push_back(*p);
+    return HOT_OK;
+  };
+  hot_status st;
+  const size_t es = lay.elem_size;
+  for (int b = 0; b < 3; ++b)
+    if ((st = A(&sb[b], (size_t)lay.state_elems * es)) != HOT_OK) return st;
+  if ((st = A((void**)&ab, lay.ab_len * 8)) != HOT_OK) return st;
+  for (int q = 0; q < 2; ++q) {
+    if ((st = A((void**)&rowsum[q], lay.rs_len * 8)) != HOT_OK) return st;
+    if ((st = A((void**)&colpart[q], lay.cp_len * 8)) != HOT_OK) return st;
+  }
+  if ((st = A((void**)&kitem, lay.items.size() * kKI * 8)) != HOT_OK) return st;
+  if ((st = A((void**)&arr, lay.arr_len * 8)) != HOT_OK) return st;
+  if ((st = A((void**)&vec, lay.vec_len * 8)) != HOT_OK) return st;
+  if ((st = A((void**)&items_d, lay.items.size() * sizeof(SlabItem))) != HOT_OK) return st;
+  if ((st = A((void**)&blocks_d, lay.blocks.size() * sizeof(PBlock))) != HOT_OK) return st;
+  if ((st = A((void**)&geo_d, lay.geo.size() * sizeof(PairGeo))) != HOT_OK) return st;
+  if ((st = A((void**)&ctl_d, lay.geo.size() * sizeof(PairCtl) * 2)) != HOT_OK) return st;
+  if ((st = A((void**)&stats_d, lay.geo.size() * 2 * 8 * 8)) != HOT_OK) return st;
+  if ((st = A((void**)&ptrs_d, lay.geo.size() * 2 * (sizeof(void*) + 8))) != HOT_OK) return st;
+  if (hipHostMalloc((void**)&host_ctl, lay.geo.size() * sizeof(PairCtl) * 2) != hipSuccess) {
+    host_ctl = nullptr;
+    if (ctx) ctx->err = "hipHostMalloc failed";
+    return HOT_E_NOMEM;
+  }
+  args.items = items_d;
+  args.nitems = (int)lay.items.size();
+  args.blocks = blocks_d;
+  args.nblocks = (int)lay.blocks.size();
+  args.geo = geo_d;
+  args.ctl[0] = ctl_d;
+  args.ctl[1] = ctl_d + lay.geo.size();
+  for (int b = 0; b < 3; ++b) args.sb[b] = sb[b];
+  args.ab = ab;
+  args.rowsum[0] = rowsum[0];
+  args.rowsum[1] = rowsum[1];
+  args.colpart[0] = colpart[0];
+  args.colpart[1] = colpart[1];
+  args.kitem = kitem;
+  args.arr = arr;
+  args.vec = vec;
+  args.fp32 = lay.fp32;
+  args.maxvpl = lay.maxvpl;
+  return HOT_OK;
+}
+
+}  // namespace hot
+
+static hot_status validate_problem(hot_ctx* ctx, const hot_problem* p) {
+  if (!p) {
+    ctx->err = "null problem";
+    return HOT_E_INVALID;
+  }
+  if (p->m < 1 || p->n < 1 || p->m > kMaxSide || p->n > kMaxSide) {
+    ctx->err = "grid sides must be in [1, " + std::to_string(kMaxSide) + "]";
+    return HOT_E_INVALID;
+  }
+  if (!p->mu1 || !p->mu2) {
+    ctx->err = "null histogram pointer";
+    return HOT_E_INVALID;
+  }
+  const bool fixed = (p->flags & HOT_FLAG_FIXED_ITERS) != 0;
+  if (!fixed && !(p->tol > 0.0) ) {
+    ctx->err = "tol must be > 0";
+    return HOT_E_INVALID;
+  }
+  if (p->max_iter < 1 || p->check_every < 1) {
+    ctx->err = "max_iter and check_every must be >= 1";
+    return HOT_E_INVALID;
+  }
+  if (p->prec != HOT_FP64 && p->prec != HOT_FP32_STREAM) {
+    ctx->err = "unknown precision";
+    return HOT_E_INVALID;
+  }
+  if (!std::isfinite(p->sigma)) {
+    ctx->err = "sigma must be finite";
+    return HOT_E_INVALID;
+  }
+  return HOT_OK;
+}
+
+namespace hot {
+
+// Validate histograms on the device, compute ||b|| and sigma, fill control
+// blocks, copy tables and clear the state.  Synchronises `st` once.
+hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st) {
+  const size_t np = lay.geo.size();
+  std::vector<const double*> ptrs(2 * np);
+  std::vector<int64_t> lens(2 * np);
+  for (size_t p = 0; p < np; ++p) {
+    ptrs[2 * p] = probs[p].mu1;
+    ptrs[2 * p + 1] = probs[p].mu2;
+    lens[2 * p] = lens[2 * p + 1] = (int64_t)probs[p].m * probs[p].n;
+  }
+  (void)count;
+  const double** pd = (const double**)ptrs_d;
+  int64_t* ld = (int64_t*)((char*)ptrs_d + np * 2 * sizeof(void*));
+  HIPCK(hipMemcpyAsync(pd, ptrs.data(), np * 2 * sizeof(void*), hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(ld, lens.data(), np * 2 * 8, hipMemcpyHostToDevice, st));
+  launch_hist_stats_multi(pd, ld, (int)(2 * np), stats_d, st);
+  HIPCK(hipGetLastError());
+  std::vector<double> stats(np * 2 * 8);
+  HIPCK(hipMemcpyAsync(stats.data(), stats_d, stats.size() * 8, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  for (size_t p = 0; p < np; ++p) {
+    const double* s1 = &stats[(2 * p) * 8];
+    const double* s2 = &stats[(2 * p + 1) * 8];
+    // s[0] min, s[1] sum, s[2] non-finite count, s[3] sum of squares, s[4] last entry
+    if (s1[2] > 0 || s2[2] > 0) {
+      ctx->err = "histogram has non-finite entries (problem " + std::to_string(p) + ")";
+      return HOT_E_INVALID;
+    }
+    if (s1[0] < 0 || s2[0] < 0) {
+      ctx->err = "histogram has negative entries (problem " + std::to_string(p) + ")";
+      return HOT_E_INVALID;
+    }
+    const double tot = std::max(s1[1], s2[1]);
+    if (!(tot > 0) || std::fabs(s1[1] - s2[1]) > 1e-9 * tot) {
+      ctx->err = "histogram totals differ or are zero (problem " + std::to_string(p) + ")";
+      return HOT_E_INVALID;
+    }
+    PairGeo& g = lay.geo[p];
+    g.norm_b = std::sqrt(std::max(0.0, s1[3] + s2[3] - s2[4] * s2[4]));
+  }
+  HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), np * sizeof(PairGeo), hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(items_d, lay.items.data(), lay.items.size() * sizeof(SlabItem),
+                       hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(blocks_d, lay.blocks.data(), lay.blocks.size() * sizeof(PBlock),
+                       hipMemcpyHostToDevice, st));
+  std::vector<PairCtl> c0(np * 2);
+  std::memset(c0.data(), 0, c0.size() * sizeof(PairCtl));
+  for (size_t p = 0; p < np; ++p) {
+    const hot_problem& pr = probs[p];
+    PairCtl& c = c0[p];
+    const double nb = lay.geo[p].norm_b, nc = lay.geo[p].norm_c;
+    c.sigma = pr.sigma > 0 ? pr.sigma : ((nc > 0 && nb > 0) ? nb / nc : 1.0);
+    c.tol = pr.tol;
+    c.lam = 0.5;
+    c.k = 0;
+    c.it = 0;
+    c.status = ST_RUNNING;
+    c.mode = MODE_INIT;
+    c.src = 0;
+    c.dst = 1;
+    c.anc = -1;
+    c.max_iter = pr.max_iter;
+    c.T = pr.check_every;
+    c.flags = (int32_t)pr.flags;
+    c0[np + p] = c;
+    c0[np + p].mode = MODE_IDLE;
+  }
+  HIPCK(hipMemcpyAsync(ctl_d, c0.data(), c0.size() * sizeof(PairCtl), hipMemcpyHostToDevice, st));
+  for (size_t p = 0; p < np; ++p) {
+    const PairGeo& g = lay.geo[p];
+    launch_setup_mu(probs[p].mu1, probs[p].mu2, g.m, g.n, arr + arr_mu1T(g), arr + arr_mu2(g),
+                    st);
+  }
+  HIPCK(hipGetLastError());
+  HIPCK(hipMemsetAsync(sb[0], 0, (size_t)lay.state_elems * lay.elem_size, st));
+  for (int q = 0; q < 2; ++q) {
+    HIPCK(hipMemsetAsync(rowsum[q], 0, lay.rs_len * 8, st));
+    HIPCK(hipMemsetAsync(colpart[q], 0, lay.cp_len * 8, st));
+  }
+  HIPCK(hipMemsetAsync(ab, 0, lay.ab_len * 8, st));
+  HIPCK(hipMemsetAsync(kitem, 0, lay.items.size() * kKI * 8, st));
+  return HOT_OK;
+}
+
+static bool use_graphs() {
+  const char* e = std::getenv("HOT_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+// Run graph launches until every problem has stopped.
+hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
+  const size_t np = lay.geo.size();
+  const bool graphs = use_graphs();
+  if (graphs && !graph_exec) {
+    HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < kGraphIters; ++i) launch_iteration(args, i & 1, st);
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (e != hipSuccess) {
+      ctx->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+      return HOT_E_DEVICE;
+    }
+    HIPCK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+  }
+  hipEvent_t ev[2];
+  HIPCK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  PairCtl* hc[2] = {host_ctl, host_ctl + np};
+  int64_t launched = 0;
+  hot_status result = HOT_OK;
+  auto launch_one = [&](int slot) -> hipError_t {
+    hipError_t e;
+    if (graphs) {
+      e = hipGraphLaunch(graph_exec, st);
+    } else {
+      for (int i = 0; i < kGraphIters; ++i) launch_iteration(args, i & 1, st);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(hc[slot], ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(ev[slot], st);
+  };
+  hipError_t e = launch_one(0);
+  launched = 1;
+  int cur = 0;
+  while (e == hipSuccess) {
+    // keep one graph in flight while the previous one's status is read
+    if (launched < max_graphs) {
+      e = launch_one(cur ^ 1);
+      if (e != hipSuccess) break;
+      ++launched;
+    }
+    e = hipEventSynchronize(ev[cur]);
+    if (e != hipSuccess) break;
+    bool all_done = true;
+    for (size_t p = 0; p < np; ++p)
+      if (hc[cur][p].status == ST_RUNNING) all_done = false;
+    if (all_done || launched >= max_graphs) {
+      if (launched > 1 && !all_done) {
+        // last launched graph: wait for it too
+        e = hipEventSynchronize(ev[cur ^ 1]);
+      }
+      break;
+    }
+    cur ^= 1;
+  }
+  if (e != hipSuccess) {
+    ctx->err = std::string("iteration launch failed: ") + hipGetErrorString(e);
+    result = HOT_E_DEVICE;
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (result == HOT_OK) {
+    // the final control blocks: after whole graphs the latest copy is ctl[0]
+    e = hipMemcpy(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      ctx->err = std::string("status copy failed: ") + hipGetErrorString(e);
+      result = HOT_E_DEVICE;
+    }
+  }
+  return result;
+}
+
+static hot_status status_of(int32_t s) {
+  switch (s) {
+    case ST_CONVERGED:
+    case ST_FIXED_DONE:
+      return HOT_OK;
+    case ST_MAXITER:
+      return HOT_E_NOT_CONVERGED;
+    case ST_NUMERIC:
+      return HOT_E_NUMERIC;
+    default:
+      return HOT_E_NOT_CONVERGED;
+  }
+}
+
+void Workspace::fill_result(int p, hot_result* r, double seconds) const {
+  const PairCtl& c = host_ctl[p];
+  std::memset(r, 0, sizeof(*r));
+  r->primal_obj = c.pobj;
+  r->dual_obj = c.dobj;
+  r->kkt = c.kkt;
+  r->res_primal = c.res_p;
+  r->res_dual = c.res_d;
+  r->res_comp = c.res_c;
+  r->sigma = c.sigma;
+  r->seconds = seconds;
+  r->iters = c.it;
+  r->restarts = c.restarts;
+  r->status = (int32_t)status_of(c.status);
+}
+
+}  // namespace hot
+
+struct hot_solution {
+  std::shared_ptr<Workspace> ws;
+  int pair = 0;
+  int32_t m = 0, n = 0;
+  const double* mu1 = nullptr;  // caller's histograms (device), needed by the repair
+  const double* mu2 = nullptr;
+  int prec = 0;
+};
+
+struct hot_batch {
+  hot_ctx* ctx = nullptr;
+  std::shared_ptr<Workspace> ws;
+  std::thread th;
+  hot_status status = HOT_OK;
+  double seconds = 0;
+  int count = 0;
+};
+
+extern "C" {
+
+const char* hot_status_string(hot_status s) {
+  switch (s) {
+    case HOT_OK: return "ok";
+    case HOT_E_INVALID: return "invalid argument";
+    case HOT_E_NOMEM: return "out of device memory";
+    case HOT_E_DEVICE: return "device error";
+    case HOT_E_NOT_CONVERGED: return "not converged";
+    case HOT_E_BUSY: return "busy";
+    case HOT_E_CANCELLED: return "cancelled";
+    case HOT_E_NUMERIC: return "non-finite value in iteration";
+  }
+  return "unknown status";
+}
+
+hot_status hot_ctx_create(int device, hot_ctx** out) {
+  if (!out) return HOT_E_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= device || device < 0) {
+    (void)hipGetLastError();
+    return HOT_E_DEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) return HOT_E_DEVICE;
+  hot_ctx* c = new hot_ctx();
+  c->device = device;
+  const char* e = std::getenv("HOT_ITEM_ELEMS");
+  if (e) c->tune.item_elems = std::max<int64_t>(1024, std::atoll(e));
+  *out = c;
+  return HOT_OK;
+}
+
+void hot_ctx_destroy(hot_ctx* ctx) { delete ctx; }
+
+const char* hot_ctx_last_error(const hot_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags) {
+  (void)flags;
+  Layout lay;
+  std::string err;
+  if (prec != HOT_FP64 && prec != HOT_FP32_STREAM) return 0;
+  if (!build_layout({{m, n}}, prec == HOT_FP32_STREAM, default_tuning(), lay, err)) return 0;
+  return lay.bytes();
+}
+
+int64_t hot_plan_capacity(int32_t m, int32_t n) {
+  if (m < 1 || n < 1) return 0;
+  const int64_t M = (int64_t)m * n;
+  return M * (m + n - 1) + 2 * M - 1;
+}
+
+}  // extern "C"
+
+namespace hot {
+
+hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
+                          std::shared_ptr<Workspace>& out) {
+  if (count < 1) {
+    ctx->err = "count must be >= 1";
+    return HOT_E_INVALID;
+  }
+  std::vector<std::pair<int, int>> shapes;
+  int prec = probs[0].prec;
+  for (int p = 0; p < count; ++p) {
+    hot_status s = validate_problem(ctx, &probs[p]);
+    if (s != HOT_OK) return s;
+    if (probs[p].prec != prec) {
+      ctx->err = "all problems of a batch must use the same precision";
+      return HOT_E_INVALID;
+    }
+    shapes.push_back({probs[p].m, probs[p].n});
+  }
+  auto ws = std::make_shared<Workspace>();
+  std::string err;
+  if (!build_layout(shapes, prec == HOT_FP32_STREAM, ctx->tune, ws->lay, err)) {
+    ctx->err = err;
+    return HOT_E_INVALID;
+  }
+  ws->device = ctx->device;
+  hot_status s = ws->alloc_all(ctx);
+  if (s != HOT_OK) return s;
+  if (hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking) != hipSuccess) {
+    ctx->err = "stream creation failed";
+    return HOT_E_DEVICE;
+  }
+  ws->own_stream = true;
+  out = ws;
+  return HOT_OK;
+}
+
+}  // namespace hot
+
+extern "C" {
+
+hot_status hot_solve(hot_ctx* ctx, const hot_problem* prob, hot_stream_t stream,
+                     hot_solution** sol_out, hot_result* res) {
+  if (!ctx || !res) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->err.clear();
+  if (sol_out) *sol_out = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return HOT_E_DEVICE;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::shared_ptr<Workspace> ws;
+  hot_status s = make_workspace(ctx, prob, 1, ws);
+  if (s != HOT_OK) return s;
+  hipStream_t st = ws->stream;
+  // order after the caller's stream
+  hipEvent_t ev;
+  HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCK(hipEventRecord(ev, (hipStream_t)stream));
+  HIPCK(hipStreamWaitEvent(st, ev, 0));
+  (void)hipEventDestroy(ev);
+  s = ws->setup(ctx, prob, 1, st);
+  if (s != HOT_OK) return s;
+  const int64_t max_graphs = (int64_t)prob->max_iter * 2 / kGraphIters + 8;
+  s = ws->run(ctx, st, max_graphs);
+  if (s != HOT_OK) return s;
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  ws->fill_result(0, res, secs);
+  if (sol_out) {
+    hot_solution* so = new hot_solution();
+    so->ws = ws;
+    so->pair = 0;
+    so->m = prob->m;
+    so->n = prob->n;
+    so->mu1 = prob->mu1;
+    so->mu2 = prob->mu2;
+    so->prec = prob->prec;
+    *sol_out = so;
+  }
+  return (hot_status)res->status;
+}
+
+void hot_solution_free(hot_solution* sol) { delete sol; }
+
+hot_status hot_solution_export(hot_ctx* ctx, const hot_solution* sol, hot_stream_t stream,
+                               double* xbar, double* ybar, double* zbar, double* s) {
+  if (!ctx || !sol) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const int64_t m = sol->m, n = sol->n;
+  const int64_t N = m * m * n + m * n * n, M = m * n;
+  hipStream_t st = (hipStream_t)stream;
+  if (xbar || zbar || s) launch_export(sol->ws->args, 0, sol->pair, N, xbar, zbar, s, st);
+  if (ybar) launch_export_y(sol->ws->args, sol->pair, 3 * M - 1, ybar, st);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));
+  return HOT_OK;
+}
+
+hot_status hot_aat_solve(hot_ctx* ctx, int32_t m, int32_t n, const double* R, double* y,
+                         hot_stream_t stream) {
+  if (!ctx || !R || !y) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (m < 1 || n < 1 || m > kMaxSide || n > kMaxSide) {
+    ctx->err = "grid sides out of range";
+    return HOT_E_INVALID;
+  }
+  auto ws = std::make_shared<Workspace>();
+  std::string err;
+  if (!build_layout({{m, n}}, 0, ctx->tune, ws->lay, err)) {
+    ctx->err = err;
+    return HOT_E_INVALID;
+  }
+  hot_status s = ws->alloc_all(ctx);
+  if (s != HOT_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCK(hipMemcpyAsync(ws->geo_d, ws->lay.geo.data(), sizeof(PairGeo), hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(ws->blocks_d, ws->lay.blocks.data(), ws->lay.blocks.size() * sizeof(PBlock),
+                       hipMemcpyHostToDevice, st));
+  launch_aat_solve(ws->args, 0, (int64_t)m * n, R, st);
+  launch_export_y(ws->args, 0, 3 * (int64_t)m * n - 1, y, st);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));
+  return HOT_OK;
+}
+
+hot_status hot_batch_submit(hot_ctx* ctx, const hot_problem* probs, int32_t count,
+                            hot_stream_t stream, hot_batch** out) {
+  if (!ctx || !probs || !out || count < 1) return HOT_E_INVALID;
+  *out = nullptr;
+  std::shared_ptr<Workspace> ws;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) return HOT_E_DEVICE;
+    hot_status s = make_workspace(ctx, probs, count, ws);
+    if (s != HOT_OK) return s;
+    hipStream_t st = ws->stream;
+    hipEvent_t ev;
+    HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCK(hipEventRecord(ev, (hipStream_t)stream));
+    HIPCK(hipStreamWaitEvent(st, ev, 0));
+    (void)hipEventDestroy(ev);
+    s = ws->setup(ctx, probs, count, st);
+    if (s != HOT_OK) return s;
+  }
+  int64_t max_it = 1;
+  for (int p = 0; p < count; ++p) max_it = std::max<int64_t>(max_it, probs[p].max_iter);
+  hot_batch* b = new hot_batch();
+  b->ctx = ctx;
+  b->ws = ws;
+  b->count = count;
+  const int64_t max_graphs = max_it * 2 / kGraphIters + 8;
+  const int dev = ctx->device;
+  b->th = std::thread([b, max_graphs, dev]() {
+    (void)hipSetDevice(dev);
+    const auto t0 = std::chrono::steady_clock::now();
+    hot_ctx tmp;  // private error sink for the worker thread
+    b->status = b->ws->run(&tmp, b->ws->stream, max_graphs);
+    if (b->status != HOT_OK) {
+      std::lock_guard<std::mutex> lk(b->ctx->mu);
+      b->ctx->err = tmp.err;
+    }
+    b->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  });
+  *out = b;
+  return HOT_OK;
+}
+
+hot_status hot_batch_wait(hot_batch* b, hot_result* results) {
+  if (!b) return HOT_E_INVALID;
+  if (b->th.joinable()) b->th.join();
+  hot_status s = b->status;
+  if (s == HOT_OK && results)
+    for (int p = 0; p < b->count; ++p) b->ws->fill_result(p, &results[p], b->seconds);
+  delete b;
+  return s;
+}
+
+}  // extern "C"

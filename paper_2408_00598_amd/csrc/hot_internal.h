@@ -1,0 +1,122 @@
+// Internal data layout of libhot (not part of the C ABI).
+//
+// Storage of the flow state ("slab form" of the reduced model, Sec. 2.1):
+//   family 0 (f1): n slabs F1^(j), each m x m, F1^(j)[k][i] = f1_{i,k,j};
+//   family 1 (f2): m slabs F2^(k), each n x n, F2^(k)[j][l] = f2_{k,j,l}.
+// Each slab is row-major with a row pitch P >= L (P a multiple of the 16-byte
+// vector width); padding entries hold zero.  On a slab of side L the cost is
+// C[p][q] = (p - q)^2 for both families, and A^T y restricted to the slab is
+// alpha[p] + beta[q] with
+//   F1^(j): alpha = y1[j][.] (row index k), beta = y2[j][.] (column index i);
+//   F2^(k): alpha = -y1[.][k] (row index j), beta = y3[.][k] (column index l),
+// so A x is made of the row and column sums of the slabs.
+//
+// The iteration is kept in the single-vector form s = x/sigma + z (the
+// shadow sequence of the appendix, u = C^T w, scaled by 1/sqrt(sigma)):
+//   R = b/sigma - A(s - c),  A A^T ybar = R,  g = c - A^T ybar,
+//   xbar = sigma (s - g),  zbar = max(0, 2g - s),  shat = |s - 2g|,
+//   s <- lam s0 + (1 - lam) shat,  lam = 1/(k+2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hot {
+
+constexpr int kWG = 256;        // threads per workgroup of every kernel
+constexpr int kKI = 8;          // per-item KKT partials written by the slab pass
+constexpr int kKP = 12;         // per-block partials written by the pair reduce
+constexpr int kMaxSide = 1024;  // largest supported m or n
+
+enum Mode : int32_t {
+  MODE_IDLE = 0,
+  MODE_NORMAL = 1,   // plain update pass
+  MODE_CHECK = 2,    // update pass + KKT / fixed-point partials of w_bar^k
+  MODE_RESTART = 3,  // write sbar = max(s - g, g) into the anchor buffer
+  MODE_INIT = 4      // s = 0: only the first linear solve runs
+};
+
+enum PairStatus : int32_t {
+  ST_RUNNING = 0,
+  ST_CONVERGED = 1,
+  ST_MAXITER = 2,
+  ST_NUMERIC = 3,
+  ST_FIXED_DONE = 4
+};
+
+// per-item partial indices (slab pass, check mode)
+enum KItem : int { KI_DUAL = 0, KI_COMP, KI_XX, KI_ZZ, KI_CX, KI_FP };
+// per-block partial indices (pair reduce, check mode)
+enum KPart : int { KP_DUAL = 0, KP_COMP, KP_XX, KP_ZZ, KP_CX, KP_FP, KP_PRIM, KP_BY };
+
+struct FamGeo {
+  int32_t L;       // slab side
+  int32_t P;       // row pitch in elements
+  int32_t nslab;   // slabs in the family
+  int32_t nchunk;  // row chunks per slab (one slab-pass item each)
+  int32_t rpc;     // rows per chunk
+  int32_t lrs;     // log2(lanes per row)
+  int32_t vpl;     // 16-byte vectors per lane per row
+  int32_t pad;
+  int64_t soff;    // element offset of slab 0 in each state buffer
+  int64_t aboff;   // double offset of slab 0's alpha; beta follows (2L per slab)
+  int64_t rsoff;   // double offset of the row sums (L per slab)
+  int64_t cpoff;   // double offset of the column partials (nchunk*L per slab)
+  int64_t sumoff;  // double offset of (sum alpha, sum beta) per slab (2 per slab)
+};
+
+struct PairGeo {
+  int32_t m, n;
+  int32_t item0, nitem;  // slab-pass items of this pair
+  int32_t blk0, nblk;    // pair-level blocks of this pair
+  int32_t jpb, kpb;      // j rows / k rows per pair-level block
+  int32_t ipb, pad;      // slab items per pair-level block (KKT reduction)
+  FamGeo f[2];
+  int64_t moff;          // double offset of the M-sized arrays (5 of them)
+  int64_t voff;          // double offset of the small vectors
+  double norm_b, norm_c; // ||b||, ||c|| of the reduced model
+};
+
+// M-sized arrays at moff: mu1T[j][i], mu2[k][l], R1[j][k], R2[j][i], R3T[k][l]
+__host__ __device__ inline int64_t arr_mu1T(const PairGeo& g) { return g.moff; }
+__host__ __device__ inline int64_t arr_mu2(const PairGeo& g) { return g.moff + (int64_t)g.m * g.n; }
+__host__ __device__ inline int64_t arr_R1(const PairGeo& g) { return g.moff + 2 * (int64_t)g.m * g.n; }
+__host__ __device__ inline int64_t arr_R2(const PairGeo& g) { return g.moff + 3 * (int64_t)g.m * g.n; }
+__host__ __device__ inline int64_t arr_R3T(const PairGeo& g) { return g.moff + 4 * (int64_t)g.m * g.n; }
+// small vectors at voff: a[n], b1[n], PR3[m], S1part[nblk][m], kpart[nblk][kKP]
+__host__ __device__ inline int64_t vec_a(const PairGeo& g) { return g.voff; }
+__host__ __device__ inline int64_t vec_b1(const PairGeo& g) { return g.voff + g.n; }
+__host__ __device__ inline int64_t vec_PR3(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n; }
+__host__ __device__ inline int64_t vec_S1(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n + g.m; }
+__host__ __device__ inline int64_t vec_kpart(const PairGeo& g) {
+  return g.voff + 2 * (int64_t)g.n + g.m + (int64_t)g.nblk * g.m;
+}
+__host__ __device__ inline int64_t vec_size(const PairGeo& g) {
+  return 2 * (int64_t)g.n + g.m + (int64_t)g.nblk * g.m + (int64_t)g.nblk * kKP;
+}
+
+struct SlabItem {
+  int32_t pair, fam, slab, chunk;
+};
+
+struct PBlock {
+  int32_t pair, blk;
+};
+
+struct PairCtl {
+  double sigma, lam, tol;
+  double r_start, r_prev;
+  double kkt, res_p, res_d, res_c, pobj, dobj, fp_res;
+  int32_t k, it, restarts, status;
+  int32_t mode, src, dst, anc;
+  int32_t max_iter, T, flags, pad;
+};
+
+// closed form of sum_{q=0}^{L-1} (p - q)^2 (exact in FP64 for L <= 2^17)
+__host__ __device__ inline double cost_rowsum(int L, int p) {
+  const double dL = (double)L, dp = (double)p;
+  const double s1 = dL * (dL - 1.0) * 0.5;
+  const double s2 = (dL - 1.0) * dL * (2.0 * dL - 1.0) / 6.0;
+  return dL * dp * dp - 2.0 * dp * s1 + s2;
+}
+
+}  // namespace hot

@@ -1,0 +1,91 @@
+// Host-side runtime structures of libhot (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/hot.h"
+#include "hot_internal.h"
+
+namespace hot {
+
+// Iterations captured per graph launch (even: control blocks alternate parity).
+constexpr int kGraphIters = 20;
+
+struct Tuning {
+  int64_t item_elems;   // target elements per slab-pass workgroup
+  int rows_per_block;   // j (or k) rows per pair-level block
+};
+Tuning default_tuning();
+
+struct LaunchArgs {
+  const SlabItem* items = nullptr;
+  int nitems = 0;
+  const PBlock* blocks = nullptr;
+  int nblocks = 0;
+  const PairGeo* geo = nullptr;
+  PairCtl* ctl[2] = {nullptr, nullptr};
+  void* sb[3] = {nullptr, nullptr, nullptr};
+  double* ab = nullptr;
+  double* rowsum[2] = {nullptr, nullptr};
+  double* colpart[2] = {nullptr, nullptr};
+  double* kitem = nullptr;
+  double* arr = nullptr;
+  double* vec = nullptr;
+  int fp32 = 0;
+  int maxvpl = 1;
+};
+
+struct Layout {
+  int fp32 = 0;
+  int elem_size = 8;
+  std::vector<PairGeo> geo;
+  std::vector<SlabItem> items;
+  std::vector<PBlock> blocks;
+  int64_t state_elems = 0, ab_len = 0, rs_len = 0, cp_len = 0, arr_len = 0, vec_len = 0;
+  int maxvpl = 1;
+  size_t bytes() const;
+};
+
+bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
+                  Layout& lay, std::string& err);
+
+struct Workspace {
+  int device = 0;
+  Layout lay;
+  LaunchArgs args;
+  std::vector<void*> allocs;
+  void* sb[3] = {nullptr, nullptr, nullptr};
+  double* ab = nullptr;
+  double* rowsum[2] = {nullptr, nullptr};
+  double* colpart[2] = {nullptr, nullptr};
+  double* kitem = nullptr;
+  double* arr = nullptr;
+  double* vec = nullptr;
+  SlabItem* items_d = nullptr;
+  PBlock* blocks_d = nullptr;
+  PairGeo* geo_d = nullptr;
+  PairCtl* ctl_d = nullptr;
+  double* stats_d = nullptr;
+  void* ptrs_d = nullptr;
+  PairCtl* host_ctl = nullptr;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
+  ~Workspace();
+  void release();
+  hot_status alloc_all(hot_ctx* ctx);
+  hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
+  hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
+  void fill_result(int p, hot_result* r, double seconds) const;
+};
+
+hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
+                          std::shared_ptr<Workspace>& out);
+
+}  // namespace hot

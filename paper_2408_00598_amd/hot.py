@@ -1,0 +1,259 @@
+"""Python binding of libhot (argument marshalling only).
+
+Every numerical step runs in the HIP kernels of ``lib/libhot.so``; this module
+only moves pointers, sizes and streams across the C ABI declared in
+``include/hot.h``.  PyTorch provides device memory and the current stream.
+If the library is missing the import of ``lib()`` raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libhot.so")
+
+HOT_OK, HOT_E_INVALID, HOT_E_NOMEM, HOT_E_DEVICE, HOT_E_NOT_CONVERGED = 0, 1, 2, 3, 4
+HOT_E_BUSY, HOT_E_CANCELLED, HOT_E_NUMERIC = 5, 6, 7
+HOT_FP64, HOT_FP32_STREAM = 0, 1
+HOT_FLAG_RESTART, HOT_FLAG_FIXED_ITERS = 0x1, 0x2
+
+EXPORTED = [
+    "hot_ctx_create", "hot_ctx_destroy", "hot_ctx_last_error", "hot_status_string",
+    "hot_footprint_bytes", "hot_plan_capacity", "hot_solve", "hot_solution_export",
+    "hot_solution_free", "hot_recover_plan", "hot_aat_solve", "hot_batch_submit",
+    "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
+    "hot_server_stats", "hot_server_destroy",
+]
+
+
+class Problem(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("mu1", C.c_void_p), ("mu2", C.c_void_p),
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
+                ("sigma", C.c_double), ("prec", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("primal_obj", C.c_double), ("dual_obj", C.c_double), ("kkt", C.c_double),
+                ("res_primal", C.c_double), ("res_dual", C.c_double), ("res_comp", C.c_double),
+                ("sigma", C.c_double), ("seconds", C.c_double), ("iters", C.c_int32),
+                ("restarts", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+class HotError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)} ({status}): {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libhot.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libhot.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.hot_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+    L.hot_ctx_destroy.argtypes = [vp]
+    L.hot_ctx_last_error.argtypes = [vp]
+    L.hot_ctx_last_error.restype = C.c_char_p
+    L.hot_status_string.argtypes = [C.c_int]
+    L.hot_status_string.restype = C.c_char_p
+    L.hot_footprint_bytes.argtypes = [i32, i32, i32, C.c_uint32]
+    L.hot_footprint_bytes.restype = C.c_size_t
+    L.hot_plan_capacity.argtypes = [i32, i32]
+    L.hot_plan_capacity.restype = i64
+    L.hot_solve.argtypes = [vp, C.POINTER(Problem), vp, C.POINTER(vp), C.POINTER(Result)]
+    L.hot_solution_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.hot_solution_free.argtypes = [vp]
+    L.hot_aat_solve.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.hot_batch_submit.argtypes = [vp, C.POINTER(Problem), i32, vp, C.POINTER(vp)]
+    L.hot_batch_wait.argtypes = [vp, C.POINTER(Result)]
+    if hasattr(L, "hot_recover_plan"):
+        L.hot_recover_plan.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64),
+                                       C.POINTER(dbl)]
+    for name in EXPORTED:
+        if hasattr(L, name):
+            getattr(L, name).restype = getattr(L, name).restype or C.c_int
+    L.hot_ctx_destroy.restype = None
+    L.hot_solution_free.restype = None
+    _lib = L
+    return L
+
+
+def status_string(s):
+    try:
+        return lib().hot_status_string(int(s)).decode()
+    except Exception:  # pragma: no cover - only while the library is missing
+        return str(s)
+
+
+def footprint_bytes(m, n, prec=HOT_FP64, flags=HOT_FLAG_RESTART):
+    return int(lib().hot_footprint_bytes(m, n, prec, flags))
+
+
+def plan_capacity(m, n):
+    return int(lib().hot_plan_capacity(m, n))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t
+
+
+class Context:
+    """Owns a hot_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        L = lib()
+        h = C.c_void_p()
+        st = L.hot_ctx_create(device, C.byref(h))
+        if st != HOT_OK:
+            raise HotError(st, "hot_ctx_create failed (no usable GPU?)")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hot_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return lib().hot_ctx_last_error(self.h).decode()
+
+    def problem(self, mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
+                prec=HOT_FP64, flags=HOT_FLAG_RESTART):
+        mu1, mu2 = _dev_f64(mu1), _dev_f64(mu2)
+        m, n = mu1.shape
+        if tuple(mu2.shape) != (m, n):
+            raise ValueError("histogram shapes differ")
+        return Problem(m, n, mu1.data_ptr(), mu2.data_ptr(), tol, max_iter, check_every, sigma,
+                       prec, flags)
+
+    def solve(self, mu1, mu2, keep=False, stream=None, raise_on_error=True, **kw):
+        """Run hot_solve; returns (result dict, Solution or None)."""
+        prob = self.problem(mu1, mu2, **kw)
+        res = Result()
+        sol = C.c_void_p()
+        st = lib().hot_solve(self.h, C.byref(prob), _stream_ptr(stream),
+                             C.byref(sol) if keep else None, C.byref(res))
+        if st not in (HOT_OK, HOT_E_NOT_CONVERGED) and raise_on_error:
+            raise HotError(st, self.last_error())
+        out = res.as_dict()
+        out["return_status"] = st
+        solution = Solution(self, sol, prob.m, prob.n, (mu1, mu2)) if keep and sol else None
+        return out, solution
+
+    def aat_solve(self, m, n, R, stream=None):
+        import torch
+        R = _dev_f64(R)
+        y = torch.empty(3 * m * n - 1, dtype=torch.float64, device=R.device)
+        st = lib().hot_aat_solve(self.h, m, n, C.c_void_p(R.data_ptr()),
+                                 C.c_void_p(y.data_ptr()), _stream_ptr(stream))
+        if st != HOT_OK:
+            raise HotError(st, self.last_error())
+        return y
+
+    def batch_submit(self, pairs, stream=None, **kw):
+        """pairs: list of (mu1, mu2) CUDA tensors.  Returns a Batch handle."""
+        probs = (Problem * len(pairs))(*[self.problem(a, b, **kw) for a, b in pairs])
+        h = C.c_void_p()
+        st = lib().hot_batch_submit(self.h, probs, len(pairs), _stream_ptr(stream), C.byref(h))
+        if st != HOT_OK:
+            raise HotError(st, self.last_error())
+        return Batch(self, h, len(pairs), pairs, probs)
+
+    def batch_solve(self, pairs, **kw):
+        return self.batch_submit(pairs, **kw).wait()
+
+
+class Batch:
+    def __init__(self, ctx, h, count, keep_alive, probs):
+        self.ctx, self.h, self.count = ctx, h, count
+        self._keep = (keep_alive, probs)
+
+    def wait(self):
+        res = (Result * self.count)()
+        st = lib().hot_batch_wait(self.h, res)
+        self.h = None
+        if st != HOT_OK:
+            raise HotError(st, self.ctx.last_error())
+        return [r.as_dict() for r in res]
+
+
+class Solution:
+    """Device-resident final iterate of one solve."""
+
+    def __init__(self, ctx, h, m, n, keep_alive):
+        self.ctx, self.h, self.m, self.n = ctx, h, m, n
+        self._keep = keep_alive
+
+    def free(self):
+        if self.h:
+            lib().hot_solution_free(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self, stream=None):
+        """Return (xbar, ybar, zbar, s) as float64 CUDA tensors in paper order."""
+        import torch
+        m, n = self.m, self.n
+        N, M3 = m * m * n + m * n * n, 3 * m * n - 1
+        dev = torch.device("cuda", self.ctx.device)
+        xb = torch.empty(N, dtype=torch.float64, device=dev)
+        zb = torch.empty(N, dtype=torch.float64, device=dev)
+        s = torch.empty(N, dtype=torch.float64, device=dev)
+        yb = torch.empty(M3, dtype=torch.float64, device=dev)
+        st = lib().hot_solution_export(self.ctx.h, self.h, _stream_ptr(stream),
+                                       C.c_void_p(xb.data_ptr()), C.c_void_p(yb.data_ptr()),
+                                       C.c_void_p(zb.data_ptr()), C.c_void_p(s.data_ptr()))
+        if st != HOT_OK:
+            raise HotError(st, self.ctx.last_error())
+        return xb, yb, zb, s
+
+    def recover_plan(self, stream=None, capacity=None):
+        """Algorithm 1 + marginal repair.  Returns (src, dst, mass, marg_err[4])."""
+        import torch
+        cap = capacity or plan_capacity(self.m, self.n)
+        dev = torch.device("cuda", self.ctx.device)
+        src = torch.empty(cap, dtype=torch.int32, device=dev)
+        dst = torch.empty(cap, dtype=torch.int32, device=dev)
+        mass = torch.empty(cap, dtype=torch.float64, device=dev)
+        nnz = C.c_int64()
+        err = (C.c_double * 4)()
+        st = lib().hot_recover_plan(self.ctx.h, self.h, _stream_ptr(stream),
+                                    C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                    C.c_void_p(mass.data_ptr()), cap, C.byref(nnz), err)
+        if st != HOT_OK:
+            raise HotError(st, self.ctx.last_error())
+        k = nnz.value
+        return src[:k], dst[:k], mass[:k], list(err)

@@ -1,0 +1,92 @@
+"""GPU parity against the FP64 oracle, through the C ABI.
+
+* Prop. 3 solve (hot_aat_solve) against the oracle's W-hat form.
+* Fixed-iteration trajectories (Alg. 2 verbatim, no restarts): the GPU's
+  single-vector iterate s = x/sigma + z, and w_bar = (y_bar, z_bar, x_bar),
+  equal the oracle's (y, z, x) iteration after k = 1, 10, 100 updates.
+* Converged solves with the restart rule: same iteration count and objective
+  within 1e-6 relative (FP64), 1e-4 (FP32 streams).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import ctx, dev, need_gpu, rel
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1), (1, 9), (9, 1), (2, 3), (6, 6), (5, 7), (7, 5), (32, 32), (17, 40)]
+
+
+def hist(rng, m, n, zeros=0.0):
+    h = rng.uniform(0.05, 1.0, size=(m, n))
+    if zeros:
+        h[rng.uniform(size=(m, n)) < zeros] = 0
+        if h.sum() == 0:
+            h[0, 0] = 1
+    return h / h.sum()
+
+
+@pytest.mark.parametrize("m,n", SHAPES + [(64, 48), (100, 3)])
+def test_aat_solve_matches_oracle(oracle, m, n):
+    need_gpu()
+    rng = np.random.default_rng(m * 1000 + n)
+    R = rng.standard_normal(3 * m * n - 1)
+    y_or = oracle.solve_aat(m, n, R)
+    c = ctx()
+    y = c.aat_solve(m, n, dev(R)).cpu().numpy()
+    assert rel(y, y_or) <= 1e-12
+    # and the residual through the oracle's A, A^T
+    r = oracle.A(m, n, oracle.AT(m, n, y)) - R
+    assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(R) * (m + n)
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_fixed_iteration_trajectory_fp64(oracle, m, n, k):
+    need_gpu()
+    from paper_2408_00598_amd import hot
+    rng = np.random.default_rng(7 * m + n + k)
+    mu1, mu2 = hist(rng, m, n, 0.1), hist(rng, m, n, 0.1)
+    c = ctx()
+    res, sol = c.solve(dev(mu1), dev(mu2), keep=True, max_iter=k,
+                       flags=hot.HOT_FLAG_FIXED_ITERS)
+    xb, yb, zb, s = (t.cpu().numpy() for t in sol.export())
+    oxb, oyb, ozb, os_, ores = oracle.hot(mu1, mu2, fixed_iters=k, restart=False)
+    assert res["iters"] == k
+    assert rel(s, os_) <= 1e-10
+    assert rel(yb, oyb) <= 1e-10
+    assert rel(xb, oxb) <= 1e-9
+    assert rel(zb, ozb) <= 1e-9
+    assert abs(res["primal_obj"] - ores["primal_obj"]) <= 1e-9 * max(abs(ores["primal_obj"]), 1e-12)
+    assert abs(res["sigma"] - ores["sigma"]) <= 1e-14 * ores["sigma"]
+
+
+@pytest.mark.parametrize("m,n,tol", [(6, 6, 1e-6), (8, 8, 1e-6), (5, 9, 1e-8), (32, 32, 1e-6),
+                                     (32, 32, 1e-4)])
+def test_converged_solve_fp64(oracle, m, n, tol):
+    need_gpu()
+    from paper_2408_00598_amd import workloads
+    rng = np.random.default_rng(workloads.seed_for(0, m + n))
+    mu1, mu2 = workloads.gaussian_blobs(m, n, 3, rng), workloads.gaussian_blobs(m, n, 3, rng)
+    c = ctx()
+    res, _ = c.solve(dev(mu1), dev(mu2), tol=tol, max_iter=200000)
+    _, _, _, _, ores = oracle.hot(mu1, mu2, tol=tol, max_iter=200000)
+    assert res["status"] == 0 and ores["converged"] == 1
+    assert res["iters"] == ores["iters"]
+    assert res["restarts"] == ores["restarts"]
+    assert abs(res["primal_obj"] - ores["primal_obj"]) <= 1e-6 * abs(ores["primal_obj"])
+    assert abs(res["kkt"] - ores["kkt"]) <= 1e-6 * ores["kkt"] + 1e-15
+    assert res["kkt"] <= tol
+
+
+@pytest.mark.parametrize("m,n", [(8, 8), (32, 32), (20, 28)])
+def test_converged_solve_fp32_streams(oracle, m, n):
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    rng = np.random.default_rng(workloads.seed_for(0, 7 * m + n))
+    mu1, mu2 = workloads.gaussian_blobs(m, n, 3, rng), workloads.gaussian_blobs(m, n, 3, rng)
+    c = ctx()
+    res, _ = c.solve(dev(mu1), dev(mu2), tol=1e-6, max_iter=200000, prec=hot.HOT_FP32_STREAM)
+    _, _, _, _, ores = oracle.hot(mu1, mu2, tol=1e-6, max_iter=200000)
+    assert res["status"] == 0
+    assert abs(res["primal_obj"] - ores["primal_obj"]) <= 1e-4 * abs(ores["primal_obj"])
