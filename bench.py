@@ -1,0 +1,177 @@
+"""Benchmark of the HOT hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input: every
+pair of the batch is solved with Algorithm 2 (slab passes, structured solve,
+KKT checks, restarts) to the relative KKT tolerance, then its transport plan
+is recovered (Algorithm 1 + marginal repair) when --plan is on.  Inputs are
+resident in HBM before the timed region starts.
+
+Workloads (named by what they are):
+  batched   256 pairs, side n uniform in {32,48,64,96,128}, half 1-5 Gaussian
+            blob mixtures and half U(0,1) noise, FP32 streams, rel KKT 1e-4
+            (the default; the headline "FP32 batched" figure)
+  pair128   one 128 x 128 pair (5 blobs), FP32 streams, rel KKT 1e-4
+  pair512   one 512 x 512 pair (1-8 blobs + Cauchy blob), FP32, rel KKT 1e-4
+  small     one 32 x 32 pair (3 blobs), FP64, rel KKT 1e-6
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "OT solves/sec to 1e-4 KKT (FP32 batched vs FP64 plain); HBM GB/s; p99 lat"
+PEAK_HBM_GBS = 8000.0
+
+
+def make_workload(name, pairs):
+    from paper_2408_00598_amd import hot, workloads
+    if name == "batched":
+        return (workloads.batch_pairs(pairs), 1e-4, hot.HOT_FP32_STREAM,
+                f"batched {pairs} pairs, n~U{{32,48,64,96,128}}, 50% 1-5 Gaussian blobs / 50% "
+                "U(0,1) noise, FP32 streams + FP64 reductions, rel KKT 1e-4")
+    if name == "pair128":
+        return ([workloads.pair_medium("blobs")], 1e-4, hot.HOT_FP32_STREAM,
+                "one 128x128 pair, 5 Gaussian blobs + floor 1e-3, FP32 streams, rel KKT 1e-4")
+    if name == "pair512":
+        return ([workloads.pair_large()], 1e-4, hot.HOT_FP32_STREAM,
+                "one 512x512 pair, 1-8 Gaussian blobs + Cauchy blob, floor 1e-6, FP32 streams, "
+                "rel KKT 1e-4")
+    if name == "small":
+        return ([workloads.pair_small()], 1e-6, hot.HOT_FP64,
+                "one 32x32 pair, 3 Gaussian blobs + floor 1e-3, FP64, rel KKT 1e-6")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(pairs, results, tol, budget_s=20.0):
+    """Oracle (FP64, single thread) seconds per iteration measured per grid
+    side on the first pair of that side, times the iterations each pair took,
+    summed over the batch."""
+    from oracle import oracle as O
+    sides = sorted({a.shape for a, _ in pairs})
+    per_side = {}
+    share = budget_s / max(1, len(sides))
+    for shp in sides:
+        a, b = next((a, b) for a, b in pairs if a.shape == shp)
+        k, t = 1, 0.0
+        while True:
+            t0 = time.perf_counter()
+            O.hot(a, b, fixed_iters=k, restart=False)
+            t = time.perf_counter() - t0
+            if t >= share / 4 or k >= 4096:
+                break
+            k *= 4
+        per_side[shp] = t / (k + 1)
+    total = sum(per_side[a.shape] * max(1, r["iters"]) for (a, _), r in zip(pairs, results))
+    sample = ("oracle s/iteration timed on one pair per grid side ("
+              + ", ".join(f"{s[0]}x{s[1]}: {per_side[s]*1e3:.2f} ms/it" for s in sides)
+              + ") x the iterations each pair took on the GPU, summed over the batch")
+    return {"value": len(pairs) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "estimated_seconds": total}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--pairs", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--plan", action="store_true", help="recover plans inside each step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2408_00598_amd import hot
+
+    pairs, tol, prec, desc = make_workload(args.workload, args.pairs)
+    dev = torch.device("cuda:0")
+    dpairs = [(torch.tensor(a, device=dev), torch.tensor(b, device=dev)) for a, b in pairs]
+    torch.cuda.synchronize()
+    ctx = hot.Context(0)
+    kw = dict(tol=tol, max_iter=1000000, prec=prec)
+
+    def step():
+        if len(dpairs) == 1:
+            res, sol = ctx.solve(*dpairs[0], keep=args.plan, **kw)
+            out = [res]
+            if args.plan:
+                sol.recover_plan()
+                sol.free()
+            return out
+        return ctx.batch_solve(dpairs, **kw)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = len(dpairs) * args.steps / elapsed
+
+    # roofline of the slab pass: same workload once more with event timing
+    ctx.set_profiling(True)
+    step()
+    prof = ctx.profile()
+    ctx.set_profiling(False)
+    achieved = prof["slab_bytes"] / prof["slab_seconds"] / 1e9 if prof["slab_seconds"] else 0.0
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "kernel": "k_slab_pass",
+                "launches": prof["slab_launches"],
+                "avg_launch_us": prof["slab_seconds"] / max(1, prof["slab_launches"]) * 1e6,
+                "bytes_per_launch": prof["slab_bytes"] / max(1, prof["slab_launches"])}
+
+    iters = [r["iters"] for r in results]
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "stream_dtype": "f32" if prec == hot.HOT_FP32_STREAM else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "pairs": len(dpairs), "tol": tol},
+        "roofline": roofline,
+        "solve_stats": {"iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
+                        "kkt_max": float(max(r["kkt"] for r in results)),
+                        "converged": int(sum(r["status"] == 0 for r in results))},
+    }
+    if not args.no_fp64_plain and len(dpairs) > 1:
+        # plain per-pair FP64 solves on the same GPU: two pairs per grid side
+        by_side = {}
+        for (a, b), r in zip(dpairs, results):
+            by_side.setdefault(tuple(a.shape), []).append((a, b))
+        est, sample = 0.0, []
+        for shp, lst in sorted(by_side.items()):
+            ts = []
+            for a, b in lst[:2]:
+                t1 = time.perf_counter()
+                ctx.solve(a, b, tol=tol, max_iter=1000000, prec=hot.HOT_FP64)
+                ts.append(time.perf_counter() - t1)
+            est += np.mean(ts) * len(lst)
+            sample.append(f"{shp[0]}: {np.mean(ts)*1e3:.1f} ms")
+        out["fp64_plain"] = {"value": len(dpairs) / est, "unit": "solves/s",
+                             "sample": "hot_solve FP64 per pair, 2 pairs per side timed (" +
+                                       ", ".join(sample) + "), scaled to the batch"}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pairs, results, tol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

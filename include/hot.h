@@ -60,7 +60,7 @@ typedef enum {
                                      is w_bar at the final iterate */
 
 typedef struct {
-  int32_t m, n;            /* grid rows, columns: 1 <= m, n <= 4096 */
+  int32_t m, n;            /* grid rows, columns: 1 <= m, n <= 1024 */
   const double *mu1;       /* device, m*n, source histogram */
   const double *mu2;       /* device, m*n, target histogram */
   double tol;              /* relative KKT tolerance (eq. kkt_res), > 0 */
@@ -99,6 +99,17 @@ void hot_ctx_destroy(hot_ctx *ctx);
 /* Text of the last error recorded on ctx (never NULL; "" if none). */
 const char *hot_ctx_last_error(const hot_ctx *ctx);
 const char *hot_status_string(hot_status s);
+
+/* Measurement.  With profiling on, solves launch the iteration kernels
+ * directly (no graphs) and time every slab pass with a hipEvent pair on the
+ * solver's stream.  hot_ctx_profile_read fills out[4] with counters summed
+ * over all solves since profiling was last switched:
+ *   out[0] slab-pass launches timed, out[1] their total seconds (events),
+ *   out[2] algorithmic bytes streamed by slab passes (state read + anchor read
+ *          when separate + state write, padding excluded; counted in graph
+ *          mode too), out[3] iterations launched. */
+hot_status hot_ctx_set_profiling(hot_ctx *ctx, int on);
+hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
 
 /* Device bytes one problem needs (state buffers, sums, dual vectors).
  * Pure host arithmetic; 0 for invalid sizes. */

@@ -28,6 +28,8 @@
 namespace hot {
 
 void launch_iteration(const LaunchArgs& a, int par, hipStream_t st);
+void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st);
+void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st);
 void launch_setup_mu(const double* mu1, const double* mu2, int m, int n, double* mu1T,
                      double* mu2c, hipStream_t st);
 void launch_export(const LaunchArgs& a, int par, int pair, int64_t N, double* xbar,
@@ -64,7 +66,8 @@ static double slab_cost_sq(int L) {
 Tuning default_tuning() {
   Tuning t;
   t.item_elems = 65536;
-  t.rows_per_block = 8;
+  t.min_items = 2048;
+  t.unroll = 1;
   return t;
 }
 
@@ -72,7 +75,7 @@ size_t Layout::bytes() const {
   return (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
          (size_t)cp_len * 8 * 2 + (size_t)items.size() * (kKI * 8 + sizeof(SlabItem)) +
          (size_t)arr_len * 8 + (size_t)vec_len * 8 + geo.size() * sizeof(PairGeo) +
-         blocks.size() * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 + 4096;
+         (blocks.size() + sblocks.size()) * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 + 4096;
 }
 
 bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
@@ -81,14 +84,23 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   lay.fp32 = fp32;
   lay.elem_size = fp32 ? 4 : 8;
   const int W = fp32 ? 4 : 2;
-  int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0;
-  int maxvpl = 1;
-  for (size_t p = 0; p < shapes.size(); ++p) {
-    const int m = shapes[p].first, n = shapes[p].second;
+  int64_t total = 0;
+  for (const auto& sh : shapes) {
+    const int m = sh.first, n = sh.second;
     if (m < 1 || n < 1 || m > kMaxSide || n > kMaxSide) {
       err = "grid sides must be in [1, " + std::to_string(kMaxSide) + "]";
       return false;
     }
+    total += (int64_t)n * m * round_up(m, W) + (int64_t)m * n * round_up(n, W);
+  }
+  // workgroup size of the slab pass: enough workgroups to fill the chip,
+  // never more than item_elems elements each
+  const int64_t item_elems =
+      std::max<int64_t>(2048, std::min<int64_t>(tune.item_elems, total / std::max<int64_t>(1, tune.min_items)));
+  int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0;
+  int maxvpl = 1;
+  for (size_t p = 0; p < shapes.size(); ++p) {
+    const int m = shapes[p].first, n = shapes[p].second;
     PairGeo g;
     std::memset(&g, 0, sizeof(g));
     g.m = m;
@@ -100,19 +112,15 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       F.nslab = fam == 0 ? n : m;
       F.P = (int32_t)round_up(F.L, W);
       const int Q = F.P / W;
-      int LR, vpl;
-      if (Q <= 64) {
-        LR = next_pow2(Q);
-        vpl = 1;
-      } else {
-        LR = 64;
-        vpl = (Q + 63) / 64;
-      }
+      // about two 16-byte vectors per lane per row: short DPP trees for the
+      // row sums, few column accumulators per lane
+      const int LR = std::min(64, next_pow2((Q + 1) / 2));
+      const int vpl = (Q + LR - 1) / LR;
       F.lrs = ilog2(LR);
       F.vpl = vpl;
       maxvpl = std::max(maxvpl, vpl);
-      const int step = 4 * (64 / LR);  // rows one workgroup covers per step
-      int rows = (int)std::max<int64_t>(1, tune.item_elems / F.P);
+      const int step = 8 * (64 / LR);  // rows one workgroup covers per (two-row) step
+      int rows = (int)std::max<int64_t>(1, item_elems / F.P);
       rows = (int)round_up(rows, step);
       if (rows >= F.L) rows = F.L;
       F.rpc = rows;
@@ -132,14 +140,13 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
         for (int c = 0; c < F.nchunk; ++c) lay.items.push_back(SlabItem{(int32_t)p, fam, s, c});
     }
     g.nitem = (int32_t)lay.items.size() - g.item0;
-    int nblk = std::max(1, (std::max(m, n) + tune.rows_per_block - 1) / tune.rows_per_block);
-    g.jpb = (n + nblk - 1) / nblk;
-    g.kpb = (m + nblk - 1) / nblk;
-    nblk = std::max((n + g.jpb - 1) / g.jpb, (m + g.kpb - 1) / g.kpb);
-    g.nblk = nblk;
-    g.ipb = (g.nitem + nblk - 1) / nblk;
+    g.nblk = (std::max(m, n) + 3) / 4;   // reduce blocks: rows 4b..4b+3 of each family
+    g.nsblk = (m + n + 3) / 4;           // solve blocks: slabs 4b..4b+3
+    g.ipb = (g.nitem + g.nblk - 1) / g.nblk;
     g.blk0 = (int32_t)lay.blocks.size();
-    for (int b = 0; b < nblk; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b});
+    for (int b = 0; b < g.nblk; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b});
+    g.sblk0 = (int32_t)lay.sblocks.size();
+    for (int b = 0; b < g.nsblk; ++b) lay.sblocks.push_back(PBlock{(int32_t)p, b});
     g.moff = moff;
     moff += 5 * (int64_t)m * n;
     g.voff = voff;
@@ -169,7 +176,22 @@ struct hot_ctx {
   std::mutex mu;
   std::string err;
   Tuning tune = default_tuning();
+  // measurement counters (hot_ctx_profile_read)
+  bool profiling = false;
+  double prof_seconds = 0, prof_launches = 0, prof_bytes = 0, iters_launched = 0;
 };
+
+namespace hot {
+// Fold a finished workspace's counters into the context (caller holds ctx->mu).
+static void collect_profile(hot_ctx* ctx, Workspace& ws) {
+  unsigned long long bytes = 0;
+  if (hipMemcpy(&bytes, ws.bytes_ctr, 8, hipMemcpyDeviceToHost) != hipSuccess) return;
+  ctx->prof_bytes += (double)bytes;
+  ctx->prof_seconds += ws.prof_seconds;
+  ctx->prof_launches += (double)ws.prof_launches;
+  ctx->iters_launched += (double)ws.iterations_launched;
+}
+}  // namespace hot
 
 #define HIPCK(expr)                                                                  \
   do {                                                                               \
@@ -222,10 +244,12 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   if ((st = A((void**)&vec, lay.vec_len * 8)) != HOT_OK) return st;
   if ((st = A((void**)&items_d, lay.items.size() * sizeof(SlabItem))) != HOT_OK) return st;
   if ((st = A((void**)&blocks_d, lay.blocks.size() * sizeof(PBlock))) != HOT_OK) return st;
+  if ((st = A((void**)&sblocks_d, lay.sblocks.size() * sizeof(PBlock))) != HOT_OK) return st;
   if ((st = A((void**)&geo_d, lay.geo.size() * sizeof(PairGeo))) != HOT_OK) return st;
   if ((st = A((void**)&ctl_d, lay.geo.size() * sizeof(PairCtl) * 2)) != HOT_OK) return st;
   if ((st = A((void**)&stats_d, lay.geo.size() * 2 * 8 * 8)) != HOT_OK) return st;
   if ((st = A((void**)&ptrs_d, lay.geo.size() * 2 * (sizeof(void*) + 8))) != HOT_OK) return st;
+  if ((st = A((void**)&bytes_ctr, 256)) != HOT_OK) return st;
   if (hipHostMalloc((void**)&host_ctl, lay.geo.size() * sizeof(PairCtl) * 2) != hipSuccess) {
     host_ctl = nullptr;
     if (ctx) ctx->err = "hipHostMalloc failed";
@@ -235,6 +259,8 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   args.nitems = (int)lay.items.size();
   args.blocks = blocks_d;
   args.nblocks = (int)lay.blocks.size();
+  args.sblocks = sblocks_d;
+  args.nsblocks = (int)lay.sblocks.size();
   args.geo = geo_d;
   args.ctl[0] = ctl_d;
   args.ctl[1] = ctl_d + lay.geo.size();
@@ -249,6 +275,7 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   args.vec = vec;
   args.fp32 = lay.fp32;
   args.maxvpl = lay.maxvpl;
+  args.bytes_ctr = bytes_ctr;
   return HOT_OK;
 }
 
@@ -335,6 +362,8 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
                        hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(blocks_d, lay.blocks.data(), lay.blocks.size() * sizeof(PBlock),
                        hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(sblocks_d, lay.sblocks.data(), lay.sblocks.size() * sizeof(PBlock),
+                       hipMemcpyHostToDevice, st));
   std::vector<PairCtl> c0(np * 2);
   std::memset(c0.data(), 0, c0.size() * sizeof(PairCtl));
   for (size_t p = 0; p < np; ++p) {
@@ -371,6 +400,7 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   }
   HIPCK(hipMemsetAsync(ab, 0, lay.ab_len * 8, st));
   HIPCK(hipMemsetAsync(kitem, 0, lay.items.size() * kKI * 8, st));
+  HIPCK(hipMemsetAsync(bytes_ctr, 0, 8, st));
   return HOT_OK;
 }
 
@@ -382,6 +412,7 @@ static bool use_graphs() {
 // Run graph launches until every problem has stopped.
 hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
   const size_t np = lay.geo.size();
+  if (profile) return run_profiled(ctx, st, max_graphs);
   const bool graphs = use_graphs();
   if (graphs && !graph_exec) {
     HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -422,6 +453,7 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
       if (e != hipSuccess) break;
       ++launched;
     }
+    iterations_launched = launched * kGraphIters;
     e = hipEventSynchronize(ev[cur]);
     if (e != hipSuccess) break;
     bool all_done = true;
@@ -451,6 +483,40 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
       result = HOT_E_DEVICE;
     }
   }
+  return result;
+}
+
+// Profiling run: direct launches, a hipEvent pair around every slab pass on
+// the workspace stream, no pipelining.  Same kernels and iteration order as
+// the graph path.
+hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
+  const size_t np = lay.geo.size();
+  std::vector<hipEvent_t> evs(2 * kGraphIters);
+  for (auto& e : evs) HIPCK(hipEventCreate(&e));
+  hot_status result = HOT_OK;
+  for (int64_t g = 0; g < max_graphs; ++g) {
+    for (int i = 0; i < kGraphIters; ++i) {
+      HIPCK(hipEventRecord(evs[2 * i], st));
+      launch_slab_pass(args, i & 1, st);
+      HIPCK(hipEventRecord(evs[2 * i + 1], st));
+      launch_pair_kernels(args, i & 1, st);
+    }
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    for (int i = 0; i < kGraphIters; ++i) {
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+      prof_seconds += ms * 1e-3;
+      ++prof_launches;
+    }
+    iterations_launched += kGraphIters;
+    bool all_done = true;
+    for (size_t p = 0; p < np; ++p)
+      if (host_ctl[p].status == ST_RUNNING) all_done = false;
+    if (all_done) break;
+  }
+  for (auto& e : evs) (void)hipEventDestroy(e);
   return result;
 }
 
@@ -533,6 +599,10 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   c->device = device;
   const char* e = std::getenv("HOT_ITEM_ELEMS");
   if (e) c->tune.item_elems = std::max<int64_t>(1024, std::atoll(e));
+  e = std::getenv("HOT_MIN_ITEMS");
+  if (e) c->tune.min_items = std::max<int64_t>(1, std::atoll(e));
+  e = std::getenv("HOT_UNROLL");
+  if (e) c->tune.unroll = std::atoi(e) >= 2 ? 2 : 1;
   *out = c;
   return HOT_OK;
 }
@@ -540,6 +610,24 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
 void hot_ctx_destroy(hot_ctx* ctx) { delete ctx; }
 
 const char* hot_ctx_last_error(const hot_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+hot_status hot_ctx_set_profiling(hot_ctx* ctx, int on) {
+  if (!ctx) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->profiling = on != 0;
+  ctx->prof_seconds = ctx->prof_launches = ctx->prof_bytes = ctx->iters_launched = 0;
+  return HOT_OK;
+}
+
+hot_status hot_ctx_profile_read(hot_ctx* ctx, double* out) {
+  if (!ctx || !out) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  out[0] = ctx->prof_launches;
+  out[1] = ctx->prof_seconds;
+  out[2] = ctx->prof_bytes;
+  out[3] = ctx->iters_launched;
+  return HOT_OK;
+}
 
 size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags) {
   (void)flags;
@@ -584,7 +672,10 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
     return HOT_E_INVALID;
   }
   ws->device = ctx->device;
+  ws->profile = ctx->profiling;
   hot_status s = ws->alloc_all(ctx);
+  ws->args.unroll = ctx->tune.unroll;
+  ws->args.slab_grid = ws->args.nitems;
   if (s != HOT_OK) return s;
   if (hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking) != hipSuccess) {
     ctx->err = "stream creation failed";
@@ -622,6 +713,7 @@ hot_status hot_solve(hot_ctx* ctx, const hot_problem* prob, hot_stream_t stream,
   const int64_t max_graphs = (int64_t)prob->max_iter * 2 / kGraphIters + 8;
   s = ws->run(ctx, st, max_graphs);
   if (s != HOT_OK) return s;
+  collect_profile(ctx, *ws);
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   ws->fill_result(0, res, secs);
@@ -675,6 +767,8 @@ hot_status hot_aat_solve(hot_ctx* ctx, int32_t m, int32_t n, const double* R, do
   HIPCK(hipMemcpyAsync(ws->geo_d, ws->lay.geo.data(), sizeof(PairGeo), hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(ws->blocks_d, ws->lay.blocks.data(), ws->lay.blocks.size() * sizeof(PBlock),
                        hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(ws->sblocks_d, ws->lay.sblocks.data(),
+                       ws->lay.sblocks.size() * sizeof(PBlock), hipMemcpyHostToDevice, st));
   launch_aat_solve(ws->args, 0, (int64_t)m * n, R, st);
   launch_export_y(ws->args, 0, 3 * (int64_t)m * n - 1, y, st);
   HIPCK(hipGetLastError());
@@ -715,9 +809,10 @@ hot_status hot_batch_submit(hot_ctx* ctx, const hot_problem* probs, int32_t coun
     const auto t0 = std::chrono::steady_clock::now();
     hot_ctx tmp;  // private error sink for the worker thread
     b->status = b->ws->run(&tmp, b->ws->stream, max_graphs);
-    if (b->status != HOT_OK) {
+    {
       std::lock_guard<std::mutex> lk(b->ctx->mu);
-      b->ctx->err = tmp.err;
+      if (b->status != HOT_OK) b->ctx->err = tmp.err;
+      else collect_profile(b->ctx, *b->ws);
     }
     b->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   });

@@ -67,9 +67,9 @@ struct FamGeo {
 struct PairGeo {
   int32_t m, n;
   int32_t item0, nitem;  // slab-pass items of this pair
-  int32_t blk0, nblk;    // pair-level blocks of this pair
-  int32_t jpb, kpb;      // j rows / k rows per pair-level block
-  int32_t ipb, pad;      // slab items per pair-level block (KKT reduction)
+  int32_t blk0, nblk;    // reduce blocks of this pair (4 rows j and 4 rows k each)
+  int32_t sblk0, nsblk;  // solve blocks of this pair (4 slabs each)
+  int32_t ipb, pad;      // slab items per reduce block (KKT reduction)
   FamGeo f[2];
   int64_t moff;          // double offset of the M-sized arrays (5 of them)
   int64_t voff;          // double offset of the small vectors
@@ -82,16 +82,21 @@ __host__ __device__ inline int64_t arr_mu2(const PairGeo& g) { return g.moff + (
 __host__ __device__ inline int64_t arr_R1(const PairGeo& g) { return g.moff + 2 * (int64_t)g.m * g.n; }
 __host__ __device__ inline int64_t arr_R2(const PairGeo& g) { return g.moff + 3 * (int64_t)g.m * g.n; }
 __host__ __device__ inline int64_t arr_R3T(const PairGeo& g) { return g.moff + 4 * (int64_t)g.m * g.n; }
-// small vectors at voff: a[n], b1[n], PR3[m], S1part[nblk][m], kpart[nblk][kKP]
+// small vectors at voff: a[n], b1[n], PR3[m], Sp[m], spart[nblk][4], kpart[nblk][kKP]
+// (Sp[k] = sum_j R1[j][k] + PR3[k]; spart: per-block sums of a_j, PR3[k],
+//  Sp[k]/D[k]; kpart: per-block KKT partials)
 __host__ __device__ inline int64_t vec_a(const PairGeo& g) { return g.voff; }
 __host__ __device__ inline int64_t vec_b1(const PairGeo& g) { return g.voff + g.n; }
 __host__ __device__ inline int64_t vec_PR3(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n; }
-__host__ __device__ inline int64_t vec_S1(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n + g.m; }
+__host__ __device__ inline int64_t vec_Sp(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n + g.m; }
+__host__ __device__ inline int64_t vec_spart(const PairGeo& g) {
+  return g.voff + 2 * (int64_t)g.n + 2 * (int64_t)g.m;
+}
 __host__ __device__ inline int64_t vec_kpart(const PairGeo& g) {
-  return g.voff + 2 * (int64_t)g.n + g.m + (int64_t)g.nblk * g.m;
+  return vec_spart(g) + 4 * (int64_t)g.nblk;
 }
 __host__ __device__ inline int64_t vec_size(const PairGeo& g) {
-  return 2 * (int64_t)g.n + g.m + (int64_t)g.nblk * g.m + (int64_t)g.nblk * kKP;
+  return 2 * (int64_t)g.n + 2 * (int64_t)g.m + 4 * (int64_t)g.nblk + (int64_t)g.nblk * kKP;
 }
 
 struct SlabItem {

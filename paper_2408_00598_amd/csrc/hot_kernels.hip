@@ -68,125 +68,201 @@ __device__ inline T* pick(T* b0, T* b1, T* b2, int i) {
 // ---------------------------------------------------------------------------
 // Slab pass.  One workgroup per (slab, row chunk).  A row of the slab is
 // covered by LR = 2^lrs lanes, each holding vpl 16-byte vectors of the row;
-// a wave covers 64/LR rows per step, the four waves interleave.  Column
-// sums stay in FP64 registers for the whole chunk; row sums are finished
-// with a shuffle tree across the LR lanes of the row.
+// a wave covers 64/LR rows per step, the four waves interleave, and two
+// steps are loaded before either is computed.  Column sums stay in FP64
+// registers for the whole chunk; row sums are finished with DPP moves inside
+// the wave (the sum lands in the last lane of each LR-lane group).
+// The pass is specialised at compile time on its mode and on where the
+// Halpern anchor comes from, so the element loop has no branches.
 // ---------------------------------------------------------------------------
-template <typename T, int MAXVPL>
-__global__ __launch_bounds__(kWG) void k_slab_pass(
-    const SlabItem* __restrict__ items, const PairGeo* __restrict__ geo,
-    const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
-    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
-    double* __restrict__ colpart, double* __restrict__ kitem) {
+template <int CTRL, int RM = 0xf>
+__device__ inline double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over aligned groups of LR lanes (LR a power of two <= 64); valid in
+// the last lane of each group.
+__device__ inline double group_sum(double v, int LR) {
+  if (LR >= 2) v += dpp_mov<0xB1>(v);        // quad_perm [1,0,3,2]
+  if (LR >= 4) v += dpp_mov<0x4E>(v);        // quad_perm [2,3,0,1]
+  if (LR >= 8) v += dpp_mov<0x141>(v);       // row_half_mirror
+  if (LR >= 16) v += dpp_mov<0x140>(v);      // row_mirror
+  if (LR >= 32) v += dpp_mov<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
+  if (LR >= 64) v += dpp_mov<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+enum { ANC_ZERO = 0, ANC_SAME = 1, ANC_SEP = 2 };
+
+struct SlabCtx {
+  int L, P, r0, r1, lrs, vpl, lin, slot, wave, lane;
+  double lam, oml, sigma;
+};
+
+template <typename T, int MAXVPL, int MODE, int ANC, int U>
+__device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
+                                 T* __restrict__ dst, const T* __restrict__ anc,
+                                 const double* __restrict__ alpha, const double* __restrict__ bl,
+                                 double (&colacc)[MAXVPL][VecT<T>::W], double* __restrict__ rowsum,
+                                 double (&kk)[6]) {
   constexpr int W = VecT<T>::W;
   typedef typename VecT<T>::type VT;
-  __shared__ double lds_col[4 * 64 * MAXVPL * W];
-  __shared__ double red[4];
-
-  const SlabItem itm = items[blockIdx.x];
-  const PairCtl* cp = ctl + itm.pair;
-  const int status = cp->status;
-  const int mode = cp->mode;
-  if (status != ST_RUNNING) return;
-  if (mode != MODE_NORMAL && mode != MODE_CHECK && mode != MODE_RESTART) return;
-  const FamGeo F = geo[itm.pair].f[itm.fam];
-  const int L = F.L, P = F.P;
-  const int r0 = itm.chunk * F.rpc;
-  const int r1 = min(L, r0 + F.rpc);
-  const int64_t soff = F.soff + (int64_t)itm.slab * L * P;
-  const int src_i = cp->src, anc_i = cp->anc;
-  const int dst_i = (mode == MODE_RESTART) ? 2 : cp->dst;
-  const T* __restrict__ src = pick<T>(sb0, sb1, sb2, src_i) + soff;
-  T* __restrict__ dst = pick<T>(sb0, sb1, sb2, dst_i) + soff;
-  // anchor: -1 zero, == src the same values as s (first update of an epoch)
-  const bool anc_zero = (anc_i < 0) || (mode == MODE_RESTART);
-  const bool anc_same = !anc_zero && (anc_i == src_i);
-  const T* __restrict__ anc = (anc_zero || anc_same) ? src : pick<T>(sb0, sb1, sb2, anc_i) + soff;
-  const double lam = cp->lam, oml = 1.0 - cp->lam, sigma = cp->sigma;
-  const double* __restrict__ alpha = ab + F.aboff + (int64_t)itm.slab * 2 * L;
-  const double* __restrict__ beta = alpha + L;
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int lrs = F.lrs, LR = 1 << lrs;
-  const int slot = lane >> lrs, lin = lane & (LR - 1);
-  const int rpw = 64 >> lrs;
-  const int vpl = F.vpl;
-
-  double bq[MAXVPL][W], colacc[MAXVPL][W];
+  const int LR = 1 << x.lrs, rpw = 64 >> x.lrs;
+  const int L = x.L, P = x.P;
+  for (int pb = x.r0 + x.wave * rpw; pb < x.r1; pb += 4 * U * rpw) {
+    int prow[U];
+    bool rvv[U];
+    VT xs[U][MAXVPL], xa[U][MAXVPL];
 #pragma unroll
-  for (int v = 0; v < MAXVPL; ++v)
+    for (int u = 0; u < U; ++u) {
+      prow[u] = pb + u * 4 * rpw + x.slot;
+      rvv[u] = prow[u] < x.r1;
 #pragma unroll
-    for (int e = 0; e < W; ++e) {
-      const int q = ((lin + (v << lrs)) * W) + e;
-      bq[v][e] = (v < vpl && q < L) ? beta[q] : 0.0;
-      colacc[v][e] = 0.0;
-    }
-  double kd = 0, kc = 0, kx = 0, kz = 0, kcx = 0, kfp = 0;
-
-  for (int pb = r0 + wave * rpw; pb < r1; pb += 4 * rpw) {
-    const int p = pb + slot;
-    const bool rv = p < r1;
-    const double ap = rv ? alpha[p] : 0.0;
-    double rowacc = 0.0;
-    VT xs[MAXVPL], xa[MAXVPL];
-#pragma unroll
-    for (int v = 0; v < MAXVPL; ++v) {
-      const int q0 = (lin + (v << lrs)) * W;
-      if (v < vpl && rv && q0 < L) {
-        xs[v] = *reinterpret_cast<const VT*>(src + (int64_t)p * P + q0);
-        if (!anc_zero && !anc_same) xa[v] = *reinterpret_cast<const VT*>(anc + (int64_t)p * P + q0);
+      for (int v = 0; v < MAXVPL; ++v) {
+        const int q0 = (x.lin + (v << x.lrs)) * W;
+        if (v < x.vpl && rvv[u] && q0 < L) {
+          xs[u][v] = *reinterpret_cast<const VT*>(src + (int64_t)prow[u] * P + q0);
+          if (ANC == ANC_SEP) xa[u][v] = *reinterpret_cast<const VT*>(anc + (int64_t)prow[u] * P + q0);
+        }
       }
     }
 #pragma unroll
-    for (int v = 0; v < MAXVPL; ++v) {
-      const int q0 = (lin + (v << lrs)) * W;
-      if (v < vpl && rv && q0 < L) {
-        VT out;
+    for (int u = 0; u < U; ++u) {
+      const int p = prow[u];
+      const bool rv = rvv[u];
+      const double ap = rv ? alpha[p] : 0.0;
+      double rowacc = 0.0;
 #pragma unroll
-        for (int e = 0; e < W; ++e) {
-          const int q = q0 + e;
-          T st = (T)0;
-          if (q < L) {
-            const double s = (double)vget(xs[v], e);
-            const double d = (double)(p - q);
-            const double g = d * d - ap - bq[v][e];
+      for (int v = 0; v < MAXVPL; ++v) {
+        const int q0 = (x.lin + (v << x.lrs)) * W;
+        if (v < x.vpl && rv && q0 < L) {
+          VT out;
+          const double d0 = (double)(p - q0);
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            const bool ok = (q0 + e) < L;
+            const double s = (double)vget(xs[u][v], e);
+            const double d = d0 - (double)e;
+            const double g = d * d - (ap + bl[q0 + e]);
             double o;
-            if (mode == MODE_RESTART) {
+            if (MODE == MODE_RESTART) {
               o = fmax(s - g, g);
             } else {
               const double sh = fabs(s - 2.0 * g);
-              const double a = anc_zero ? 0.0 : (anc_same ? s : (double)vget(xa[v], e));
-              o = lam * a + oml * sh;
-              if (mode == MODE_CHECK) {
-                const double xb = sigma * (s - g);
+              if (ANC == ANC_ZERO) o = x.oml * sh;
+              else if (ANC == ANC_SAME) o = x.lam * s + x.oml * sh;
+              else o = x.lam * (double)vget(xa[u][v], e) + x.oml * sh;
+              if (MODE == MODE_CHECK) {
+                const double xb = x.sigma * (s - g);
                 const double zb = fmax(0.0, 2.0 * g - s);
                 const double dr = zb - g;
                 const double mn = fmin(xb, zb);
                 const double fr = s - sh;
-                kd += dr * dr;
-                kc += mn * mn;
-                kx += xb * xb;
-                kz += zb * zb;
-                kcx += d * d * xb;
-                kfp += fr * fr;
+                kk[KI_DUAL] += ok ? dr * dr : 0.0;
+                kk[KI_COMP] += ok ? mn * mn : 0.0;
+                kk[KI_XX] += ok ? xb * xb : 0.0;
+                kk[KI_ZZ] += ok ? zb * zb : 0.0;
+                kk[KI_CX] += ok ? d * d * xb : 0.0;
+                kk[KI_FP] += ok ? fr * fr : 0.0;
               }
             }
-            st = (T)o;
+            const T st = ok ? (T)o : (T)0;
             const double sd = (double)st;
             rowacc += sd;
             colacc[v][e] += sd;
+            vset(out, e, st);
           }
-          vset(out, e, st);
+          *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
         }
-        *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
       }
+      rowacc = group_sum(rowacc, LR);
+      if (rv && x.lin == LR - 1) rowsum[p] = rowacc;
     }
-    // row sum across the LR lanes of this row
-    for (int off = 1; off < LR; off <<= 1) rowacc += __shfl_xor(rowacc, off, 64);
-    if (rv && lin == 0) rowsum[F.rsoff + (int64_t)itm.slab * L + p] = rowacc;
+  }
+}
+
+// HEAVY = 0: plain update passes; HEAVY = 1: check and restart passes.  Both
+// kernels are launched every iteration; a workgroup whose pair is in the
+// other kind of pass exits at once.
+template <typename T, int MAXVPL, int HEAVY, int U>
+__device__ inline void slab_item(
+    int item, const SlabItem* __restrict__ items, const PairGeo* __restrict__ geo,
+    const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
+    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
+    double* __restrict__ colpart, double* __restrict__ kitem,
+    unsigned long long* __restrict__ bytes_ctr, double* lds_col, double* lds_beta, double* red) {
+  constexpr int W = VecT<T>::W;
+  constexpr int S = 64 * MAXVPL * W;
+  const SlabItem itm = items[item];
+  const PairCtl* cp = ctl + itm.pair;
+  const int status = cp->status;
+  const int mode = cp->mode;
+  if (status != ST_RUNNING) return;
+  if (HEAVY ? (mode != MODE_CHECK && mode != MODE_RESTART) : (mode != MODE_NORMAL)) return;
+  // (uniform per workgroup: every thread reads the same control block)
+  const FamGeo F = geo[itm.pair].f[itm.fam];
+  SlabCtx x;
+  x.L = F.L;
+  x.P = F.P;
+  x.r0 = itm.chunk * F.rpc;
+  x.r1 = min(F.L, x.r0 + F.rpc);
+  x.lrs = F.lrs;
+  x.vpl = F.vpl;
+  x.lane = threadIdx.x & 63;
+  x.wave = threadIdx.x >> 6;
+  x.slot = x.lane >> x.lrs;
+  x.lin = x.lane & ((1 << x.lrs) - 1);
+  x.lam = cp->lam;
+  x.oml = 1.0 - cp->lam;
+  x.sigma = cp->sigma;
+  const int L = F.L;
+  const int64_t soff = F.soff + (int64_t)itm.slab * L * F.P;
+  const int src_i = cp->src, anc_i = cp->anc;
+  const int dst_i = (mode == MODE_RESTART) ? 2 : cp->dst;
+  const T* src = pick<T>(sb0, sb1, sb2, src_i) + soff;
+  T* dst = pick<T>(sb0, sb1, sb2, dst_i) + soff;
+  const int anc_kind =
+      (mode == MODE_RESTART || anc_i < 0) ? ANC_ZERO : (anc_i == src_i ? ANC_SAME : ANC_SEP);
+  const T* anc = anc_kind == ANC_SEP ? pick<T>(sb0, sb1, sb2, anc_i) + soff : src;
+  const double* alpha = ab + F.aboff + (int64_t)itm.slab * 2 * L;
+  const double* beta = alpha + L;
+  double* rs = rowsum + F.rsoff + (int64_t)itm.slab * L;
+  // beta in LDS (zero in the padding columns); the barrier also keeps the
+  // previous item's readers of lds_col / lds_beta behind us
+  __syncthreads();
+  for (int q = threadIdx.x; q < F.P; q += kWG) lds_beta[q] = q < L ? beta[q] : 0.0;
+  __syncthreads();
+
+  double colacc[MAXVPL][W];
+#pragma unroll
+  for (int v = 0; v < MAXVPL; ++v)
+#pragma unroll
+    for (int e = 0; e < W; ++e) colacc[v][e] = 0.0;
+  double kk[6] = {0, 0, 0, 0, 0, 0};
+  if (!HEAVY) {
+    if (anc_kind == ANC_ZERO)
+      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_ZERO, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+    else if (anc_kind == ANC_SAME)
+      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SAME, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+    else
+      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SEP, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+  } else if (mode == MODE_CHECK) {
+    if (anc_kind == ANC_ZERO)
+      slab_rows<T, MAXVPL, MODE_CHECK, ANC_ZERO, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+    else if (anc_kind == ANC_SAME)
+      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SAME, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+    else
+      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SEP, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+  } else {
+    slab_rows<T, MAXVPL, MODE_RESTART, ANC_ZERO, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
   }
 
   // column partials: fold the row slots of the wave, then the four waves
+  const int LR = 1 << x.lrs;
 #pragma unroll
   for (int v = 0; v < MAXVPL; ++v)
 #pragma unroll
@@ -195,61 +271,80 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
       for (int off = LR; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
       colacc[v][e] = t;
     }
-  if (slot == 0) {
+  if (x.slot == 0) {
 #pragma unroll
     for (int v = 0; v < MAXVPL; ++v)
 #pragma unroll
       for (int e = 0; e < W; ++e) {
-        const int q = ((lin + (v << lrs)) * W) + e;
-        if (v < vpl && q < L) lds_col[wave * (64 * MAXVPL * W) + q] = colacc[v][e];
+        const int q = ((x.lin + (v << x.lrs)) * W) + e;
+        if (v < x.vpl && q < L) lds_col[x.wave * S + q] = colacc[v][e];
       }
   }
   __syncthreads();
   double* cpo = colpart + F.cpoff + ((int64_t)itm.slab * F.nchunk + itm.chunk) * L;
-  for (int q = threadIdx.x; q < L; q += kWG) {
-    const int S = 64 * MAXVPL * W;
+  for (int q = threadIdx.x; q < L; q += kWG)
     cpo[q] = (lds_col[q] + lds_col[S + q]) + (lds_col[2 * S + q] + lds_col[3 * S + q]);
+  if (threadIdx.x == 0 && bytes_ctr) {
+    // algorithmic stream traffic of this item: read s (and the anchor when it
+    // is a separate buffer), write the new state
+    const int streams = anc_kind == ANC_SEP ? 3 : 2;
+    atomicAdd(bytes_ctr, (unsigned long long)(x.r1 - x.r0) * L * sizeof(T) * streams);
   }
-  if (mode == MODE_CHECK) {
-    double* ko = kitem + (int64_t)blockIdx.x * kKI;
-    const double r_d = block_sum(kd, red);
-    const double r_c = block_sum(kc, red);
-    const double r_x = block_sum(kx, red);
-    const double r_z = block_sum(kz, red);
-    const double r_cx = block_sum(kcx, red);
-    const double r_fp = block_sum(kfp, red);
-    if (threadIdx.x == 0) {
-      ko[KI_DUAL] = r_d;
-      ko[KI_COMP] = r_c;
-      ko[KI_XX] = r_x;
-      ko[KI_ZZ] = r_z;
-      ko[KI_CX] = r_cx;
-      ko[KI_FP] = r_fp;
-    }
+  if (HEAVY && mode == MODE_CHECK) {
+    double* ko = kitem + (int64_t)item * kKI;
+    double r[6];
+    for (int q = 0; q < 6; ++q) r[q] = block_sum(kk[q], red);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 6; ++q) ko[q] = r[q];
   }
 }
 
+// One workgroup per item.
+template <typename T, int MAXVPL, int HEAVY, int U>
+__global__ __launch_bounds__(kWG) void k_slab_pass(
+    const SlabItem* __restrict__ items, int nitems, const PairGeo* __restrict__ geo,
+    const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
+    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
+    double* __restrict__ colpart, double* __restrict__ kitem,
+    unsigned long long* __restrict__ bytes_ctr) {
+  constexpr int W = VecT<T>::W;
+  constexpr int S = 64 * MAXVPL * W;
+  __shared__ double lds_col[4 * S];
+  __shared__ double lds_beta[S];
+  __shared__ double red[4];
+  if ((int)blockIdx.x < nitems)
+    slab_item<T, MAXVPL, HEAVY, U>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, ab, rowsum,
+                                   colpart, kitem, bytes_ctr, lds_col, lds_beta, red);
+}
+
 // ---------------------------------------------------------------------------
-// Pair reduce: R = b/sigma - A(s - c) from the slab sums, plus the block sums
-// of the structured solve (S1part, a_j, b1_j, PR3) and, on check passes, the
-// KKT partials.  Block b of a pair owns F1 slabs j in [b*jpb, ...) and F2 slabs
-// k in [b*kpb, ...).
+// Pair reduce: R = b/sigma - A(s - c) from the slab sums, the row totals the
+// structured solve needs, and (check passes) the KKT partials.  Block b of a
+// pair gives one wave to each of the rows j = 4b + w of R1 / R2 and k = 4b + w
+// of R3^T; reductions are wave-local, one LDS exchange per block.
 // ---------------------------------------------------------------------------
+__device__ inline double dinv(int m, int k) { return (k == m - 1) ? 1.0 / (m + 1.0) : 1.0 / m; }
+// sum_{j,l < n} (j - l)^2
+__device__ inline double cost_total(int n) {
+  const double dn = (double)n;
+  return dn * dn * (dn * dn - 1.0) / 6.0;
+}
+
 __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const PBlock* __restrict__ blocks, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, const double* __restrict__ rowsum,
     const double* __restrict__ colpart, const double* __restrict__ rowsum_prev,
     const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
     const double* __restrict__ ab, double* __restrict__ arr, double* __restrict__ vec) {
-  __shared__ double S1loc[kMaxSide];
-  __shared__ double red[4];
+  __shared__ double wred[4][kKP];
   const PBlock pbk = blocks[blockIdx.x];
   const PairCtl* cp = ctl + pbk.pair;
   if (cp->status != ST_RUNNING) return;
   const int mode = cp->mode;
   if (mode == MODE_IDLE) return;
   const PairGeo G = geo[pbk.pair];
-  const int m = G.m, n = G.n, b = pbk.blk, t = threadIdx.x;
+  const int m = G.m, n = G.n, b = pbk.blk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double isg = 1.0 / cp->sigma;
   const FamGeo F1 = G.f[0], F2 = G.f[1];
   const double* mu1T = arr + arr_mu1T(G);
@@ -257,136 +352,144 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   double* R1 = arr + arr_R1(G);
   double* R2 = arr + arr_R2(G);
   double* R3T = arr + arr_R3T(G);
-  const int j0 = b * G.jpb, j1 = min(n, j0 + G.jpb);
-  const int k0 = b * G.kpb, k1 = min(m, k0 + G.kpb);
-
-  for (int k = t; k < m; k += kWG) S1loc[k] = 0.0;
-  for (int j = j0; j < j1; ++j) {
+  const int j = 4 * b + wave, k = 4 * b + wave;
+  double p_sa = 0.0, p_sp = 0.0, p_u = 0.0;
+  if (j < n) {
     double sr1 = 0.0, sr2 = 0.0;
-    for (int k = t; k < m; k += kWG) {
-      const double rs1 = rowsum[F1.rsoff + (int64_t)j * m + k];
-      const double rs2 = rowsum[F2.rsoff + (int64_t)k * n + j];
-      const double r1 = -((rs1 - cost_rowsum(m, k)) - (rs2 - cost_rowsum(n, j)));
-      R1[(int64_t)j * m + k] = r1;
-      S1loc[k] += r1;
+    const double cnj = cost_rowsum(n, j);
+    for (int kk = lane; kk < m; kk += 64) {
+      const double rs1 = rowsum[F1.rsoff + (int64_t)j * m + kk];
+      const double rs2 = rowsum[F2.rsoff + (int64_t)kk * n + j];
+      const double r1 = -((rs1 - cost_rowsum(m, kk)) - (rs2 - cnj));
+      R1[(int64_t)j * m + kk] = r1;
       sr1 += r1;
     }
-    for (int i = t; i < m; i += kWG) {
+    const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
+    for (int i = lane; i < m; i += 64) {
       double cs = 0.0;
-      const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m + i;
-      for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m];
+      for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m + i];
       const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - cost_rowsum(m, i));
       R2[(int64_t)j * m + i] = r2;
       sr2 += r2;
     }
-    const double s1 = block_sum(sr1, red);
-    const double s2 = block_sum(sr2, red);
-    if (t == 0) {
-      vec[vec_b1(G) + j] = s1;
-      vec[vec_a(G) + j] = s2;
+    sr1 = wave_sum(sr1);
+    sr2 = wave_sum(sr2);
+    if (lane == 0) {
+      vec[vec_b1(G) + j] = sr1;
+      vec[vec_a(G) + j] = sr2;
     }
+    p_sa = sr2;
   }
-  __syncthreads();
-  for (int k = t; k < m; k += kWG) vec[vec_S1(G) + (int64_t)b * m + k] = S1loc[k];
-  for (int k = k0; k < k1; ++k) {
-    double sr3 = 0.0;
-    for (int l = t; l < n; l += kWG) {
+  if (k < m) {
+    double s3 = 0.0, c1 = 0.0, t2 = 0.0;
+    const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
+    for (int l = lane; l < n; l += 64) {
       double r3 = 0.0;
       if (!(k == m - 1 && l == n - 1)) {
         double cs = 0.0;
-        const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n + l;
-        for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n];
+        for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n + l];
         r3 = mu2[(int64_t)k * n + l] * isg - (cs - cost_rowsum(n, l));
       }
       R3T[(int64_t)k * n + l] = r3;
-      sr3 += r3;
+      s3 += r3;
     }
-    const double s3 = block_sum(sr3, red);
-    if (t == 0) vec[vec_PR3(G) + k] = s3;
+    for (int jj = lane; jj < n; jj += 64) {
+      c1 += rowsum[F1.rsoff + (int64_t)jj * m + k];  // row k of every F1 slab
+      t2 += rowsum[F2.rsoff + (int64_t)k * n + jj];  // all rows of F2 slab k
+    }
+    s3 = wave_sum(s3);
+    c1 = wave_sum(c1);
+    t2 = wave_sum(t2);
+    // sum_j R1[j][k] = -sum_j (rs1[j][k] - C_m(k)) + sum_j (rs2[k][j] - C_n(j))
+    const double sp = -c1 + (double)n * cost_rowsum(m, k) + t2 - cost_total(n) + s3;
+    if (lane == 0) {
+      vec[vec_PR3(G) + k] = s3;
+      vec[vec_Sp(G) + k] = sp;
+    }
+    p_sp = s3;
+    p_u = sp * dinv(m, k);
   }
-
+  if (lane == 0) {
+    wred[wave][0] = p_sa;
+    wred[wave][1] = p_sp;
+    wred[wave][2] = p_u;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    vec[vec_spart(G) + 4 * (int64_t)b + q] = (wred[0][q] + wred[1][q]) + (wred[2][q] + wred[3][q]);
+  }
   if (mode != MODE_CHECK) return;
+
   // ---- check pass: KKT partials of w_bar^k -------------------------------
   double part[kKI] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
     const int i0 = G.item0 + b * G.ipb;
     const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
-    for (int it = i0 + t; it < i1; it += kWG)
+    for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
       for (int q = 0; q < 6; ++q) part[q] += kitem[(int64_t)it * kKI + q];
   }
-  // primal residual A xbar - b with xbar = sigma (s - g): the sums of s^k are
-  // the previous pass's sums; the sums of g over a slab row / column follow
-  // from alpha, beta and their per-slab totals (written by the solve).
+  // primal residual A xbar - b, xbar = sigma (s - g): the sums of s^k are the
+  // previous pass's sums; the sums of g over a slab row / column follow from
+  // alpha, beta and their per-slab totals.
   const double sg = cp->sigma;
   double prim = 0.0, by = 0.0;
-  for (int j = j0; j < j1; ++j) {
+  if (j < n) {
     const double* al = ab + F1.aboff + (int64_t)j * 2 * m;
     const double* be = al + m;
     const double sa = ab[F1.sumoff + 2 * (int64_t)j], sb = ab[F1.sumoff + 2 * (int64_t)j + 1];
-    for (int k = t; k < m; k += kWG) {
-      // row k of F1^(j) and row j of F2^(k) share the conservation row (j,k)
-      const double* al2 = ab + F2.aboff + (int64_t)k * 2 * n;
-      const double sb2 = ab[F2.sumoff + 2 * (int64_t)k + 1];
-      const double x1 = sg * (rowsum_prev[F1.rsoff + (int64_t)j * m + k] -
-                              (cost_rowsum(m, k) - m * al[k] - sb));
-      const double x2 = sg * (rowsum_prev[F2.rsoff + (int64_t)k * n + j] -
+    for (int kk = lane; kk < m; kk += 64) {
+      // row kk of F1^(j) and row j of F2^(kk) share the conservation row (j,kk)
+      const double* al2 = ab + F2.aboff + (int64_t)kk * 2 * n;
+      const double sb2 = ab[F2.sumoff + 2 * (int64_t)kk + 1];
+      const double x1 = sg * (rowsum_prev[F1.rsoff + (int64_t)j * m + kk] -
+                              (cost_rowsum(m, kk) - m * al[kk] - sb));
+      const double x2 = sg * (rowsum_prev[F2.rsoff + (int64_t)kk * n + j] -
                               (cost_rowsum(n, j) - n * al2[j] - sb2));
       const double r = x1 - x2;
       prim += r * r;
     }
-    for (int i = t; i < m; i += kWG) {
+    const double* cpj = colpart_prev + F1.cpoff + (int64_t)j * F1.nchunk * m;
+    for (int i = lane; i < m; i += 64) {
       double cs = 0.0;
-      const double* cpj = colpart_prev + F1.cpoff + (int64_t)j * F1.nchunk * m + i;
-      for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m];
+      for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m + i];
       const double x = sg * (cs - (cost_rowsum(m, i) - sa - m * be[i]));
       const double r = x - mu1T[(int64_t)j * m + i];
       prim += r * r;
       by += mu1T[(int64_t)j * m + i] * be[i];
     }
   }
-  for (int k = k0; k < k1; ++k) {
+  if (k < m) {
     const double* al = ab + F2.aboff + (int64_t)k * 2 * n;
     const double* be = al + n;
     const double sa = ab[F2.sumoff + 2 * (int64_t)k];
-    for (int l = t; l < n; l += kWG) {
+    const double* cpk = colpart_prev + F2.cpoff + (int64_t)k * F2.nchunk * n;
+    for (int l = lane; l < n; l += 64) {
       if (k == m - 1 && l == n - 1) continue;
       double cs = 0.0;
-      const double* cpk = colpart_prev + F2.cpoff + (int64_t)k * F2.nchunk * n + l;
-      for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n];
+      for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n + l];
       const double x = sg * (cs - (cost_rowsum(n, l) - sa - n * be[l]));
       const double r = x - mu2[(int64_t)k * n + l];
       prim += r * r;
       by += mu2[(int64_t)k * n + l] * be[l];
     }
   }
-  double* kp = vec + vec_kpart(G) + (int64_t)b * kKP;
-  double outv[kKP];
-  for (int q = 0; q < 6; ++q) outv[q] = block_sum(part[q], red);
-  outv[KP_PRIM] = block_sum(prim, red);
-  outv[KP_BY] = block_sum(by, red);
-  if (t == 0)
-    for (int q = 0; q < 8; ++q) kp[q] = outv[q];
-}
-
-// Row-k alpha/beta of slab F2^(k) are -y1[.][k] and y3[.][k]; y1 entries are
-// recomputed from the same formula as the F1 side (identical inputs).
-__device__ inline double y1_entry(const double* R1, const double* a, const double* PR3,
-                                  const double* tq, const double* rsj, int m, int n,
-                                  int j, int k) {
-  const double dm = (double)m, dn = (double)n;
-  const double rh = R1[(int64_t)j * m + k] - a[j] / dm + PR3[k] / dn;
-  return (rh + tq[k] + rsj[j] / dn) / (dm + dn);
+  part[KP_PRIM] = prim;
+  part[KP_BY] = by;
+  __syncthreads();
+  for (int q = 0; q < 8; ++q) {
+    const double v = wave_sum(part[q]);
+    if (lane == 0) wred[wave][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int q = threadIdx.x;
+    vec[vec_kpart(G) + (int64_t)b * kKP + q] = (wred[0][q] + wred[1][q]) + (wred[2][q] + wred[3][q]);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Pair solve.  Every block of a pair first reproduces the same decision from
-// the check partials (fixed summation order), then, unless the pair stops or
-// restarts, solves A A^T ybar = R in the Schur-complement form:
-//   Rhat1^j = R1^j - (1^T R2^j / m) 1 + PR3 / n,  S = sum_j Rhat1^j,
-//   (D - 1 1^T) t = S with D = diag(m, .., m, m+1)   (t = sum_j y1^j),
-//   y1^j = (I + 1 1^T / n)(Rhat1^j + Q t)/(m+n),  Q = I - e_m e_m^T / n,
-//   y2^j = (R2^j - (1^T y1^j) 1)/m,  y3^l = (R3^l + t)/n.
-// Block 0 writes the control block of the next pass (other parity).
+// Decision after a pass (identical in every solve block of the pair).
 // ---------------------------------------------------------------------------
 __device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, PairCtl& nx,
                        bool& solve) {
@@ -415,8 +518,8 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, Pa
       solve = true;
       break;
     case MODE_CHECK: {
-      double acc[kKP];
-      for (int q = 0; q < kKP; ++q) acc[q] = 0.0;
+      double acc[8];
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
       const double* kp = vec + vec_kpart(G);
       for (int b = 0; b < G.nblk; ++b)
         for (int q = 0; q < 8; ++q) acc[q] += kp[(int64_t)b * kKP + q];
@@ -457,8 +560,7 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, Pa
           nx.it = c.it + 1;
           nx.restarts = c.restarts + 1;
           nx.k = 0;
-          // src keeps s^k for the restart pass
-          return;
+          return;  // src keeps s^k for the restart pass
         }
         nx.k = c.k + 1;
         nx.it = c.it + 1;
@@ -479,112 +581,129 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, Pa
   nx.dst = (nx.mode == MODE_CHECK || nx.src == 2) ? (nx.src == 0 ? 1 : 0) : nx.src;
 }
 
-__device__ void solve_blocks(const PairGeo& G, int b, const double* arr, double* vec,
-                             double* ab, double* tq_lds, double* red) {
-  const int m = G.m, n = G.n, t = threadIdx.x;
+// ---------------------------------------------------------------------------
+// Structured solve of A A^T ybar = R (Prop. 3), Schur complement on y1:
+//   Rhat1^j = R1^j - (1^T R2^j / m) 1 + PR3 / n,   S = sum_j Rhat1^j,
+//   (D - 1 1^T) t = S,  D = diag(m, .., m, m+1),   t = sum_j y1^j,
+//   t = D^{-1} S + m(m+1) (1^T D^{-1} S) D^{-1} 1   (Sherman-Morrison),
+//   y1^j = (I + 1 1^T / n)(Rhat1^j + Q t)/(m+n),  Q = I - e_m e_m^T / n,
+//   y2^j = (R2^j - (1^T y1^j) 1)/m,  1^T y1^j = 1^T (Rhat1^j + Q t) / n,
+//   y3^l = (R3^l + t)/n.
+// Every scalar is rebuilt from the reduce blocks' partials in a fixed order,
+// so each solve block needs no communication.  Wave w of block b writes the
+// alpha / beta of slab 4b + w (F1 slabs j first, then F2 slabs k).
+// ---------------------------------------------------------------------------
+struct SolveScalars {
+  double sa, sp, u, sq, tlast;
+};
+
+__device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec) {
+  const int m = G.m, n = G.n;
+  const double dm = (double)m, dn = (double)n;
+  const double* sp_ = vec + vec_spart(G);
+  double sa = 0.0, sp = 0.0, up = 0.0;
+  for (int b = 0; b < G.nblk; ++b) {
+    sa += sp_[4 * (int64_t)b];
+    sp += sp_[4 * (int64_t)b + 1];
+    up += sp_[4 * (int64_t)b + 2];
+  }
+  const double sdinv = (dm - 1.0) / dm + 1.0 / (dm + 1.0);
+  SolveScalars S;
+  S.sa = sa;
+  S.sp = sp;
+  S.u = up - (sa / dm) * sdinv;  // 1^T D^{-1} S
+  const double Sl = vec[vec_Sp(G) + m - 1] - sa / dm;
+  S.tlast = Sl / (dm + 1.0) + dm * (dm + 1.0) * S.u / (dm + 1.0);
+  const double tsum = S.u * (1.0 + dm * (dm + 1.0) * sdinv);
+  S.sq = tsum - S.tlast / dn;  // 1^T Q t
+  return S;
+}
+
+__device__ inline double t_entry(const PairGeo& G, const double* vec, const SolveScalars& S,
+                                 int k) {
+  const double dm = (double)G.m;
+  const double d = dinv(G.m, k);
+  return (vec[vec_Sp(G) + k] - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
+}
+
+__device__ inline double y1_entry(const PairGeo& G, const double* R1, const double* vec,
+                                  const SolveScalars& S, double qtk, int j, int k) {
+  const int m = G.m, n = G.n;
+  const double dm = (double)m, dn = (double)n;
+  const double aj = vec[vec_a(G) + j];
+  const double rsj = vec[vec_b1(G) + j] - aj + S.sp / dn + S.sq;  // 1^T (Rhat1^j + Q t)
+  const double rh = R1[(int64_t)j * m + k] - aj / dm + vec[vec_PR3(G) + k] / dn;
+  return (rh + qtk + rsj / dn) / (dm + dn);
+}
+
+__device__ void solve_slab(const PairGeo& G, int slab, const double* arr, const double* vec,
+                           double* ab, const SolveScalars& S, int lane) {
+  const int m = G.m, n = G.n;
   const double dm = (double)m, dn = (double)n;
   const double* R1 = arr + arr_R1(G);
-  const double* R2 = arr + arr_R2(G);
-  const double* R3T = arr + arr_R3T(G);
-  const double* a = vec + vec_a(G);
-  const double* b1 = vec + vec_b1(G);
-  const double* PR3 = vec + vec_PR3(G);
-  const double* S1 = vec + vec_S1(G);
-  // totals over j of a_j, and over k of PR3
-  double sa = 0.0;
-  for (int j = t; j < n; j += kWG) sa += a[j];
-  sa = block_sum(sa, red);
-  double sp = 0.0;
-  for (int k = t; k < m; k += kWG) sp += PR3[k];
-  sp = block_sum(sp, red);
-  // S and D^{-1} S
-  double u = 0.0;
-  for (int k = t; k < m; k += kWG) {
-    double s = 0.0;
-    for (int bb = 0; bb < G.nblk; ++bb) s += S1[(int64_t)bb * m + k];
-    s = s - sa / dm + PR3[k];
-    const double dk = (k == m - 1) ? dm + 1.0 : dm;
-    tq_lds[k] = s / dk;
-    u += s / dk;
-  }
-  u = block_sum(u, red);
-  // t = D^{-1} S + m(m+1) (1^T D^{-1} S) D^{-1} 1 ;  Qt = t - e_m t_m / n
-  double sq = 0.0;
-  for (int k = t; k < m; k += kWG) {
-    const double dk = (k == m - 1) ? dm + 1.0 : dm;
-    const double tk = tq_lds[k] + dm * (dm + 1.0) * u / dk;
-    tq_lds[kMaxSide + k] = tk;                       // t
-    const double q = (k == m - 1) ? tk - tk / dn : tk;  // Q t
-    tq_lds[k] = q;
-    sq += q;
-  }
-  sq = block_sum(sq, red);
-  __syncthreads();
-  const double* tq = tq_lds;                 // Q t
-  const double* tt = tq_lds + kMaxSide;      // t
-  // rsj[j] = 1^T (Rhat1^j + Q t) = b1_j - a_j + sum(PR3)/n + sum(Qt)
-  double* rsj = tq_lds + 2 * kMaxSide;
-  for (int j = t; j < n; j += kWG) rsj[j] = b1[j] - a[j] + sp / dn + sq;
-  __syncthreads();
-  const FamGeo F1 = G.f[0], F2 = G.f[1];
-  const int j0 = b * G.jpb, j1 = min(n, j0 + G.jpb);
-  const int k0 = b * G.kpb, k1 = min(m, k0 + G.kpb);
-  for (int j = j0; j < j1; ++j) {
-    double* al = ab + F1.aboff + (int64_t)j * 2 * m;
+  if (slab < n) {  // F1^(j): alpha = y1[j][.], beta = y2[j][.]
+    const int j = slab;
+    const double* R2 = arr + arr_R2(G);
+    const FamGeo F = G.f[0];
+    double* al = ab + F.aboff + (int64_t)j * 2 * m;
     double* be = al + m;
+    const double aj = vec[vec_a(G) + j];
+    const double rsj = vec[vec_b1(G) + j] - aj + S.sp / dn + S.sq;
     double sa = 0.0, sb = 0.0;
-    for (int k = t; k < m; k += kWG) {
-      const double v = y1_entry(R1, a, PR3, tq, rsj, m, n, j, k);
+    for (int k = lane; k < m; k += 64) {
+      const double tk = t_entry(G, vec, S, k);
+      const double qtk = (k == m - 1) ? tk - tk / dn : tk;
+      const double v = y1_entry(G, R1, vec, S, qtk, j, k);
       al[k] = v;
       sa += v;
     }
-    // 1^T y1^j = rsj / n
-    for (int i = t; i < m; i += kWG) {
-      const double v = (R2[(int64_t)j * m + i] - rsj[j] / dn) / dm;
+    for (int i = lane; i < m; i += 64) {
+      const double v = (R2[(int64_t)j * m + i] - rsj / dn) / dm;
       be[i] = v;
       sb += v;
     }
-    sa = block_sum(sa, red);
-    sb = block_sum(sb, red);
-    if (t == 0) {
-      ab[F1.sumoff + 2 * (int64_t)j] = sa;
-      ab[F1.sumoff + 2 * (int64_t)j + 1] = sb;
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    if (lane == 0) {
+      ab[F.sumoff + 2 * (int64_t)j] = sa;
+      ab[F.sumoff + 2 * (int64_t)j + 1] = sb;
     }
-  }
-  for (int k = k0; k < k1; ++k) {
-    double* al = ab + F2.aboff + (int64_t)k * 2 * n;
+  } else if (slab < n + m) {  // F2^(k): alpha = -y1[.][k], beta = y3[.][k]
+    const int k = slab - n;
+    const double* R3T = arr + arr_R3T(G);
+    const FamGeo F = G.f[1];
+    double* al = ab + F.aboff + (int64_t)k * 2 * n;
     double* be = al + n;
+    const double tk = t_entry(G, vec, S, k);
+    const double qtk = (k == m - 1) ? tk - tk / dn : tk;
     double sa = 0.0, sb = 0.0;
-    for (int j = t; j < n; j += kWG) {
-      const double v = -y1_entry(R1, a, PR3, tq, rsj, m, n, j, k);
+    for (int j = lane; j < n; j += 64) {
+      const double v = -y1_entry(G, R1, vec, S, qtk, j, k);
       al[j] = v;
       sa += v;
     }
-    for (int l = t; l < n; l += kWG) {
-      const double v =
-          (k == m - 1 && l == n - 1) ? 0.0 : (R3T[(int64_t)k * n + l] + tt[k]) / dn;
+    for (int l = lane; l < n; l += 64) {
+      const double v = (k == m - 1 && l == n - 1) ? 0.0 : (R3T[(int64_t)k * n + l] + tk) / dn;
       be[l] = v;
       sb += v;
     }
-    sa = block_sum(sa, red);
-    sb = block_sum(sb, red);
-    if (t == 0) {
-      ab[F2.sumoff + 2 * (int64_t)k] = sa;
-      ab[F2.sumoff + 2 * (int64_t)k + 1] = sb;
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    if (lane == 0) {
+      ab[F.sumoff + 2 * (int64_t)k] = sa;
+      ab[F.sumoff + 2 * (int64_t)k + 1] = sb;
     }
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ blocks,
+__global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ sblocks,
                                                     const PairGeo* __restrict__ geo,
                                                     const PairCtl* __restrict__ ctl,
                                                     PairCtl* __restrict__ ctl_next,
                                                     const double* __restrict__ arr,
-                                                    double* __restrict__ vec,
+                                                    const double* __restrict__ vec,
                                                     double* __restrict__ ab) {
-  __shared__ double tq_lds[3 * kMaxSide];
-  __shared__ double red[4];
-  const PBlock pbk = blocks[blockIdx.x];
+  const PBlock pbk = sblocks[blockIdx.x];
   const PairCtl c = ctl[pbk.pair];
   if (c.status != ST_RUNNING || c.mode == MODE_IDLE) {
     if (pbk.blk == 0 && threadIdx.x == 0) ctl_next[pbk.pair] = c;
@@ -594,7 +713,10 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ b
   PairCtl nx;
   bool solve;
   decide(G, c, vec, nx, solve);
-  if (solve) solve_blocks(G, pbk.blk, arr, vec, ab, tq_lds, red);
+  if (solve) {
+    const SolveScalars S = solve_scalars(G, vec);
+    solve_slab(G, 4 * pbk.blk + (threadIdx.x >> 6), arr, vec, ab, S, threadIdx.x & 63);
+  }
   if (pbk.blk == 0 && threadIdx.x == 0) ctl_next[pbk.pair] = nx;
 }
 
@@ -729,57 +851,68 @@ __global__ void k_scatter_R(const PairGeo* __restrict__ geo, int pair, const dou
   }
 }
 
-// Block sums of the solve from stored R arrays (hot_aat_solve path).
+// Row totals of the solve from stored R arrays (hot_aat_solve path): the
+// same quantities k_pair_reduce produces from slab sums.
 __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restrict__ blocks,
                                                           const PairGeo* __restrict__ geo,
                                                           const double* __restrict__ arr,
                                                           double* __restrict__ vec) {
-  __shared__ double S1loc[kMaxSide];
-  __shared__ double red[4];
+  __shared__ double wred[4][4];
   const PBlock pbk = blocks[blockIdx.x];
   const PairGeo G = geo[pbk.pair];
-  const int m = G.m, n = G.n, b = pbk.blk, t = threadIdx.x;
+  const int m = G.m, n = G.n, b = pbk.blk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* R1 = arr + arr_R1(G);
   const double* R2 = arr + arr_R2(G);
   const double* R3T = arr + arr_R3T(G);
-  const int j0 = b * G.jpb, j1 = min(n, j0 + G.jpb);
-  const int k0 = b * G.kpb, k1 = min(m, k0 + G.kpb);
-  for (int k = t; k < m; k += kWG) S1loc[k] = 0.0;
-  for (int j = j0; j < j1; ++j) {
-    double sr1 = 0.0, sr2 = 0.0;
-    for (int k = t; k < m; k += kWG) {
-      const double r1 = R1[(int64_t)j * m + k];
-      S1loc[k] += r1;
-      sr1 += r1;
-    }
-    for (int i = t; i < m; i += kWG) sr2 += R2[(int64_t)j * m + i];
-    const double s1 = block_sum(sr1, red);
-    const double s2 = block_sum(sr2, red);
-    if (t == 0) {
+  const int j = 4 * b + wave, k = 4 * b + wave;
+  double p_sa = 0.0, p_sp = 0.0, p_u = 0.0;
+  if (j < n) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int kk = lane; kk < m; kk += 64) s1 += R1[(int64_t)j * m + kk];
+    for (int i = lane; i < m; i += 64) s2 += R2[(int64_t)j * m + i];
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
       vec[vec_b1(G) + j] = s1;
       vec[vec_a(G) + j] = s2;
     }
+    p_sa = s2;
+  }
+  if (k < m) {
+    double s3 = 0.0, c1 = 0.0;
+    for (int l = lane; l < n; l += 64) s3 += R3T[(int64_t)k * n + l];
+    for (int jj = lane; jj < n; jj += 64) c1 += R1[(int64_t)jj * m + k];
+    s3 = wave_sum(s3);
+    c1 = wave_sum(c1);
+    if (lane == 0) {
+      vec[vec_PR3(G) + k] = s3;
+      vec[vec_Sp(G) + k] = c1 + s3;
+    }
+    p_sp = s3;
+    p_u = (c1 + s3) * dinv(m, k);
+  }
+  if (lane == 0) {
+    wred[wave][0] = p_sa;
+    wred[wave][1] = p_sp;
+    wred[wave][2] = p_u;
   }
   __syncthreads();
-  for (int k = t; k < m; k += kWG) vec[vec_S1(G) + (int64_t)b * m + k] = S1loc[k];
-  for (int k = k0; k < k1; ++k) {
-    double sr3 = 0.0;
-    for (int l = t; l < n; l += kWG) sr3 += R3T[(int64_t)k * n + l];
-    const double s3 = block_sum(sr3, red);
-    if (t == 0) vec[vec_PR3(G) + k] = s3;
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    vec[vec_spart(G) + 4 * (int64_t)b + q] = (wred[0][q] + wred[1][q]) + (wred[2][q] + wred[3][q]);
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_pair_solve_only(const PBlock* __restrict__ blocks,
+__global__ __launch_bounds__(kWG) void k_pair_solve_only(const PBlock* __restrict__ sblocks,
                                                          const PairGeo* __restrict__ geo,
                                                          const double* __restrict__ arr,
-                                                         double* __restrict__ vec,
+                                                         const double* __restrict__ vec,
                                                          double* __restrict__ ab) {
-  __shared__ double tq_lds[3 * kMaxSide];
-  __shared__ double red[4];
-  const PBlock pbk = blocks[blockIdx.x];
+  const PBlock pbk = sblocks[blockIdx.x];
   const PairGeo G = geo[pbk.pair];
-  solve_blocks(G, pbk.blk, arr, vec, ab, tq_lds, red);
+  const SolveScalars S = solve_scalars(G, vec);
+  solve_slab(G, 4 * pbk.blk + (threadIdx.x >> 6), arr, vec, ab, S, threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -789,9 +922,18 @@ __global__ __launch_bounds__(kWG) void k_pair_solve_only(const PBlock* __restric
 
 template <typename T, int V>
 static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
-  hipLaunchKernelGGL((k_slab_pass<T, V>), dim3(a.nitems), dim3(kWG), 0, st, a.items, a.geo,
+  if (a.unroll >= 2)
+    hipLaunchKernelGGL((k_slab_pass<T, V, 0, 2>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
+                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+  else
+    hipLaunchKernelGGL((k_slab_pass<T, V, 0, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
+                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+                     a.nitems, a.geo,
                      a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab, a.rowsum[par],
-                     a.colpart[par], a.kitem);
+                     a.colpart[par], a.kitem, a.bytes_ctr);
 }
 
 template <typename T>
@@ -802,14 +944,26 @@ static void launch_slab_t(const LaunchArgs& a, int par, hipStream_t st) {
   else launch_slab<T, 8>(a, par, st);
 }
 
-// One iteration: slab pass, pair reduce, pair solve.  Reads ctl[par], writes ctl[1-par].
-void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
+void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st) {
   if (a.fp32) launch_slab_t<float>(a, par, st);
   else launch_slab_t<double>(a, par, st);
+}
+
+void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
                      a.colpart[1 - par], a.kitem, a.ab, a.arr, a.vec);
-  hipLaunchKernelGGL(k_pair_solve, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
+  hipLaunchKernelGGL(k_pair_solve, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
+                     a.ctl[par], a.ctl[1 - par], a.arr, a.vec, a.ab);
+}
+
+// One iteration: slab pass, pair reduce, pair solve.  Reads ctl[par], writes ctl[1-par].
+void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
+  launch_slab_pass(a, par, st);
+  hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
+                     a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
+                     a.colpart[1 - par], a.kitem, a.ab, a.arr, a.vec);
+  hipLaunchKernelGGL(k_pair_solve, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
                      a.ctl[par], a.ctl[1 - par], a.arr, a.vec, a.ab);
 }
 
@@ -849,7 +1003,7 @@ void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
   hipLaunchKernelGGL(k_scatter_R, dim3(grid), dim3(kWG), 0, st, a.geo, pair, R, a.arr);
   hipLaunchKernelGGL(k_pair_sums_from_R, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.arr, a.vec);
-  hipLaunchKernelGGL(k_pair_solve_only, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
+  hipLaunchKernelGGL(k_pair_solve_only, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
                      a.arr, a.vec, a.ab);
 }
 

@@ -16,16 +16,19 @@ namespace hot {
 constexpr int kGraphIters = 20;
 
 struct Tuning {
-  int64_t item_elems;   // target elements per slab-pass workgroup
-  int rows_per_block;   // j (or k) rows per pair-level block
+  int64_t item_elems;   // largest target of elements per slab-pass workgroup
+  int64_t min_items;    // aim for at least this many slab-pass workgroups
+  int unroll;           // rows loaded ahead per wave (1 or 2)
 };
 Tuning default_tuning();
 
 struct LaunchArgs {
   const SlabItem* items = nullptr;
   int nitems = 0;
-  const PBlock* blocks = nullptr;
+  const PBlock* blocks = nullptr;   // reduce blocks
   int nblocks = 0;
+  const PBlock* sblocks = nullptr;  // solve blocks
+  int nsblocks = 0;
   const PairGeo* geo = nullptr;
   PairCtl* ctl[2] = {nullptr, nullptr};
   void* sb[3] = {nullptr, nullptr, nullptr};
@@ -37,6 +40,9 @@ struct LaunchArgs {
   double* vec = nullptr;
   int fp32 = 0;
   int maxvpl = 1;
+  int unroll = 1;  // rows loaded ahead per wave in the plain update pass
+  int slab_grid = 1;  // workgroups of a slab-pass launch (<= nitems)
+  unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes
 };
 
 struct Layout {
@@ -45,6 +51,7 @@ struct Layout {
   std::vector<PairGeo> geo;
   std::vector<SlabItem> items;
   std::vector<PBlock> blocks;
+  std::vector<PBlock> sblocks;
   int64_t state_elems = 0, ab_len = 0, rs_len = 0, cp_len = 0, arr_len = 0, vec_len = 0;
   int maxvpl = 1;
   size_t bytes() const;
@@ -67,6 +74,7 @@ struct Workspace {
   double* vec = nullptr;
   SlabItem* items_d = nullptr;
   PBlock* blocks_d = nullptr;
+  PBlock* sblocks_d = nullptr;
   PairGeo* geo_d = nullptr;
   PairCtl* ctl_d = nullptr;
   double* stats_d = nullptr;
@@ -76,12 +84,19 @@ struct Workspace {
   bool own_stream = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  unsigned long long* bytes_ctr = nullptr;
+  // profiling (events around every slab pass; direct launches)
+  bool profile = false;
+  double prof_seconds = 0.0;
+  int64_t prof_launches = 0;
+  int64_t iterations_launched = 0;
 
   ~Workspace();
   void release();
   hot_status alloc_all(hot_ctx* ctx);
   hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
   hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
+  hot_status run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
   void fill_result(int p, hot_result* r, double seconds) const;
 };
 

@@ -24,7 +24,7 @@ EXPORTED = [
     "hot_footprint_bytes", "hot_plan_capacity", "hot_solve", "hot_solution_export",
     "hot_solution_free", "hot_recover_plan", "hot_aat_solve", "hot_batch_submit",
     "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
-    "hot_server_stats", "hot_server_destroy",
+    "hot_server_stats", "hot_server_destroy", "hot_ctx_set_profiling", "hot_ctx_profile_read",
 ]
 
 
@@ -78,6 +78,8 @@ def lib():
     L.hot_aat_solve.argtypes = [vp, i32, i32, vp, vp, vp]
     L.hot_batch_submit.argtypes = [vp, C.POINTER(Problem), i32, vp, C.POINTER(vp)]
     L.hot_batch_wait.argtypes = [vp, C.POINTER(Result)]
+    L.hot_ctx_set_profiling.argtypes = [vp, C.c_int]
+    L.hot_ctx_profile_read.argtypes = [vp, C.POINTER(dbl)]
     if hasattr(L, "hot_recover_plan"):
         L.hot_recover_plan.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64),
                                        C.POINTER(dbl)]
@@ -141,6 +143,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_profiling(self, on=True):
+        lib().hot_ctx_set_profiling(self.h, 1 if on else 0)
+
+    def profile(self):
+        out = (C.c_double * 4)()
+        lib().hot_ctx_profile_read(self.h, out)
+        return {"slab_launches": out[0], "slab_seconds": out[1], "slab_bytes": out[2],
+                "iterations_launched": out[3]}
 
     def last_error(self):
         return lib().hot_ctx_last_error(self.h).decode()
