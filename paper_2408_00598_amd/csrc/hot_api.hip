@@ -171,15 +171,6 @@ using namespace hot;
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
-struct hot_ctx {
-  int device = 0;
-  std::mutex mu;
-  std::string err;
-  Tuning tune = default_tuning();
-  // measurement counters (hot_ctx_profile_read)
-  bool profiling = false;
-  double prof_seconds = 0, prof_launches = 0, prof_bytes = 0, iters_launched = 0;
-};
 
 namespace hot {
 // Fold a finished workspace's counters into the context (caller holds ctx->mu).
@@ -552,14 +543,6 @@ void Workspace::fill_result(int p, hot_result* r, double seconds) const {
 
 }  // namespace hot
 
-struct hot_solution {
-  std::shared_ptr<Workspace> ws;
-  int pair = 0;
-  int32_t m = 0, n = 0;
-  const double* mu1 = nullptr;  // caller's histograms (device), needed by the repair
-  const double* mu2 = nullptr;
-  int prec = 0;
-};
 
 struct hot_batch {
   hot_ctx* ctx = nullptr;
@@ -723,8 +706,6 @@ hot_status hot_solve(hot_ctx* ctx, const hot_problem* prob, hot_stream_t stream,
     so->pair = 0;
     so->m = prob->m;
     so->n = prob->n;
-    so->mu1 = prob->mu1;
-    so->mu2 = prob->mu2;
     so->prec = prob->prec;
     *sol_out = so;
   }

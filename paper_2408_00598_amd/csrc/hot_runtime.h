@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -104,3 +105,20 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
                           std::shared_ptr<Workspace>& out);
 
 }  // namespace hot
+
+struct hot_ctx {
+  int device = 0;
+  std::mutex mu;
+  std::string err;
+  hot::Tuning tune = hot::default_tuning();
+  // measurement counters (hot_ctx_profile_read)
+  bool profiling = false;
+  double prof_seconds = 0, prof_launches = 0, prof_bytes = 0, iters_launched = 0;
+};
+
+struct hot_solution {
+  std::shared_ptr<hot::Workspace> ws;
+  int pair = 0;
+  int32_t m = 0, n = 0;
+  int prec = 0;
+};
