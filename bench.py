@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--plan", action="store_true", help="recover plans inside each step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (torch copy_) 5 times, for scaling "
+                         "hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -127,7 +130,7 @@ def main():
 
     # roofline of the slab pass: same workload once more with event timing
     ctx.set_profiling(True)
-    step()
+    results_prof = step()
     prof = ctx.profile()
     ctx.set_profiling(False)
     achieved = prof["slab_bytes"] / prof["slab_seconds"] / 1e9 if prof["slab_seconds"] else 0.0
@@ -168,6 +171,19 @@ def main():
         out["fp64_plain"] = {"value": len(dpairs) / est, "unit": "solves/s",
                              "sample": "hot_solve FP64 per pair, 2 pairs per side timed (" +
                                        ", ".join(sample) + "), scaled to the batch"}
+    if args.copy_calibration:
+        n = 1 << 28  # 2^28 float32 = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 5,
+                                   "GB/s": 2 * 4 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs, results, tol)
     print(json.dumps(out), flush=True)

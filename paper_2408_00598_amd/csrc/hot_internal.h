@@ -67,9 +67,11 @@ struct FamGeo {
 struct PairGeo {
   int32_t m, n;
   int32_t item0, nitem;  // slab-pass items of this pair
-  int32_t blk0, nblk;    // reduce blocks of this pair (4 rows j and 4 rows k each)
-  int32_t sblk0, nsblk;  // solve blocks of this pair (4 slabs each)
-  int32_t ipb, pad;      // slab items per reduce block (KKT reduction)
+  int32_t blk0, nblk;    // reduce row blocks of this pair (4 rows j and 4 rows k each)
+  int32_t ns1, ns2;      // reduce strip blocks: 64 columns k of rs1 / 64 columns j of rs2
+  int32_t sblk0, nsblk;  // solve row blocks (4 slabs each)
+  int32_t ntj, ntk;      // solve tiles: 32 j x 32 k each
+  int32_t ipb, pad;      // slab items per reduce row block (KKT reduction)
   FamGeo f[2];
   int64_t moff;          // double offset of the M-sized arrays (5 of them)
   int64_t voff;          // double offset of the small vectors
@@ -82,21 +84,30 @@ __host__ __device__ inline int64_t arr_mu2(const PairGeo& g) { return g.moff + (
 __host__ __device__ inline int64_t arr_R1(const PairGeo& g) { return g.moff + 2 * (int64_t)g.m * g.n; }
 __host__ __device__ inline int64_t arr_R2(const PairGeo& g) { return g.moff + 3 * (int64_t)g.m * g.n; }
 __host__ __device__ inline int64_t arr_R3T(const PairGeo& g) { return g.moff + 4 * (int64_t)g.m * g.n; }
-// small vectors at voff: a[n], b1[n], PR3[m], Sp[m], spart[nblk][4], kpart[nblk][kKP]
-// (Sp[k] = sum_j R1[j][k] + PR3[k]; spart: per-block sums of a_j, PR3[k],
-//  Sp[k]/D[k]; kpart: per-block KKT partials)
+// small vectors at voff (per pair):
+//   a[n]    row totals of R2 (a_j = 1^T R2^j)
+//   tot1[n] row totals of the F1 row sums (sum_k rs1[j][k])
+//   u2[n]   column totals of the F2 row sums (sum_k rs2[k][j])
+//   b1[n]   1^T R1^j when R is given directly (Prop. 3 entry point)
+//   PR3[m]  row totals of R3^T,  tot2[m] sum_j rs2[k][j],  u1[m] sum_j rs1[j][k]
+//   Sp[m]   sum_j R1[j][k] + PR3[k] when R is given directly
+//   spart[nblk + ns1][4]  per-block partials of (sum a_j, sum PR3, sum Sp/D)
+//   kpart[nblk][kKP]      per-block KKT partials
 __host__ __device__ inline int64_t vec_a(const PairGeo& g) { return g.voff; }
-__host__ __device__ inline int64_t vec_b1(const PairGeo& g) { return g.voff + g.n; }
-__host__ __device__ inline int64_t vec_PR3(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n; }
-__host__ __device__ inline int64_t vec_Sp(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n + g.m; }
-__host__ __device__ inline int64_t vec_spart(const PairGeo& g) {
-  return g.voff + 2 * (int64_t)g.n + 2 * (int64_t)g.m;
-}
+__host__ __device__ inline int64_t vec_tot1(const PairGeo& g) { return g.voff + (int64_t)g.n; }
+__host__ __device__ inline int64_t vec_u2(const PairGeo& g) { return g.voff + 2 * (int64_t)g.n; }
+__host__ __device__ inline int64_t vec_b1(const PairGeo& g) { return g.voff + 3 * (int64_t)g.n; }
+__host__ __device__ inline int64_t vec_PR3(const PairGeo& g) { return g.voff + 4 * (int64_t)g.n; }
+__host__ __device__ inline int64_t vec_tot2(const PairGeo& g) { return vec_PR3(g) + g.m; }
+__host__ __device__ inline int64_t vec_u1(const PairGeo& g) { return vec_PR3(g) + 2 * (int64_t)g.m; }
+__host__ __device__ inline int64_t vec_Sp(const PairGeo& g) { return vec_PR3(g) + 3 * (int64_t)g.m; }
+__host__ __device__ inline int64_t vec_spart(const PairGeo& g) { return vec_PR3(g) + 4 * (int64_t)g.m; }
 __host__ __device__ inline int64_t vec_kpart(const PairGeo& g) {
-  return vec_spart(g) + 4 * (int64_t)g.nblk;
+  return vec_spart(g) + 4 * (int64_t)(g.nblk + g.ns1);
 }
 __host__ __device__ inline int64_t vec_size(const PairGeo& g) {
-  return 2 * (int64_t)g.n + 2 * (int64_t)g.m + 4 * (int64_t)g.nblk + (int64_t)g.nblk * kKP;
+  return 4 * (int64_t)g.n + 4 * (int64_t)g.m + 4 * (int64_t)(g.nblk + g.ns1) +
+         (int64_t)g.nblk * kKP;
 }
 
 struct SlabItem {
@@ -104,7 +115,7 @@ struct SlabItem {
 };
 
 struct PBlock {
-  int32_t pair, blk;
+  int32_t pair, blk, kind, pad;  // kind: see k_pair_reduce / k_pair_solve
 };
 
 struct PairCtl {

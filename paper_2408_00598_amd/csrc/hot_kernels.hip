@@ -318,10 +318,19 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
 }
 
 // ---------------------------------------------------------------------------
-// Pair reduce: R = b/sigma - A(s - c) from the slab sums, the row totals the
-// structured solve needs, and (check passes) the KKT partials.  Block b of a
-// pair gives one wave to each of the rows j = 4b + w of R1 / R2 and k = 4b + w
-// of R3^T; reductions are wave-local, one LDS exchange per block.
+// Pair reduce: R = b/sigma - A(s - c) from the slab sums, the totals the
+// structured solve needs, and (check passes) the KKT partials.
+//   kind 0, row block b: one wave per row j = 4b + w of R2 (and the total of
+//           row j of the F1 row sums) and per row k = 4b + w of R3^T (and the
+//           total of row k of the F2 row sums);
+//   kind 1, strip s: u1[k] = sum_j rs1[j][k] for 64 columns k (lane per column);
+//   kind 2, strip s: u2[j] = sum_k rs2[k][j] for 64 columns j.
+// Every access is along a row.  R1 itself is never stored: the solve reads
+// it straight from the two row-sum arrays, tile by tile.
+// With C_L(p) = sum_q (p-q)^2 and CC_L = sum_p C_L(p):
+//   R1[j][k] = -(rs1[j][k] - C_m(k)) + (rs2[k][j] - C_n(j)),
+//   1^T R1^j = -(tot1[j] - CC_m) + (u2[j] - m C_n(j)),
+//   sum_j R1[j][k] = -(u1[k] - n C_m(k)) + (tot2[k] - CC_n).
 // ---------------------------------------------------------------------------
 __device__ inline double dinv(int m, int k) { return (k == m - 1) ? 1.0 / (m + 1.0) : 1.0 / m; }
 // sum_{j,l < n} (j - l)^2
@@ -337,6 +346,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
     const double* __restrict__ ab, double* __restrict__ arr, double* __restrict__ vec) {
   __shared__ double wred[4][kKP];
+  __shared__ double strip[4][64];
   const PBlock pbk = blocks[blockIdx.x];
   const PairCtl* cp = ctl + pbk.pair;
   if (cp->status != ST_RUNNING) return;
@@ -345,25 +355,46 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   const PairGeo G = geo[pbk.pair];
   const int m = G.m, n = G.n, b = pbk.blk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double isg = 1.0 / cp->sigma;
   const FamGeo F1 = G.f[0], F2 = G.f[1];
+  if (pbk.kind != 0) {
+    // column totals of a row-sum array: lane = column, waves split the rows
+    const bool s1 = pbk.kind == 1;
+    const int ncol = s1 ? m : n, nrow = s1 ? n : m;
+    const double* rs = s1 ? rowsum + F1.rsoff : rowsum + F2.rsoff;  // [nrow][ncol]
+    const int col = 64 * b + lane;
+    double acc = 0.0;
+    if (col < ncol)
+      for (int r = wave; r < nrow; r += 4) acc += rs[(int64_t)r * ncol + col];
+    strip[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      const double tot = (strip[0][lane] + strip[1][lane]) + (strip[2][lane] + strip[3][lane]);
+      double pu = 0.0;
+      if (col < ncol) {
+        vec[(s1 ? vec_u1(G) : vec_u2(G)) + col] = tot;
+        if (s1) pu = (-(tot - (double)n * cost_rowsum(m, col))) * dinv(m, col);
+      }
+      if (s1) {
+        pu = wave_sum(pu);
+        if (lane == 0) {
+          double* sp = vec + vec_spart(G) + 4 * (int64_t)(G.nblk + b);
+          sp[0] = 0.0;
+          sp[1] = 0.0;
+          sp[2] = pu;
+        }
+      }
+    }
+    return;
+  }
+  const double isg = 1.0 / cp->sigma;
   const double* mu1T = arr + arr_mu1T(G);
   const double* mu2 = arr + arr_mu2(G);
-  double* R1 = arr + arr_R1(G);
   double* R2 = arr + arr_R2(G);
   double* R3T = arr + arr_R3T(G);
   const int j = 4 * b + wave, k = 4 * b + wave;
   double p_sa = 0.0, p_sp = 0.0, p_u = 0.0;
   if (j < n) {
-    double sr1 = 0.0, sr2 = 0.0;
-    const double cnj = cost_rowsum(n, j);
-    for (int kk = lane; kk < m; kk += 64) {
-      const double rs1 = rowsum[F1.rsoff + (int64_t)j * m + kk];
-      const double rs2 = rowsum[F2.rsoff + (int64_t)kk * n + j];
-      const double r1 = -((rs1 - cost_rowsum(m, kk)) - (rs2 - cnj));
-      R1[(int64_t)j * m + kk] = r1;
-      sr1 += r1;
-    }
+    double sr2 = 0.0, t1 = 0.0;
     const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
     for (int i = lane; i < m; i += 64) {
       double cs = 0.0;
@@ -371,17 +402,18 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - cost_rowsum(m, i));
       R2[(int64_t)j * m + i] = r2;
       sr2 += r2;
+      t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
     }
-    sr1 = wave_sum(sr1);
     sr2 = wave_sum(sr2);
+    t1 = wave_sum(t1);
     if (lane == 0) {
-      vec[vec_b1(G) + j] = sr1;
       vec[vec_a(G) + j] = sr2;
+      vec[vec_tot1(G) + j] = t1;
     }
     p_sa = sr2;
   }
   if (k < m) {
-    double s3 = 0.0, c1 = 0.0, t2 = 0.0;
+    double s3 = 0.0, t2 = 0.0;
     const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
     for (int l = lane; l < n; l += 64) {
       double r3 = 0.0;
@@ -392,22 +424,16 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       }
       R3T[(int64_t)k * n + l] = r3;
       s3 += r3;
-    }
-    for (int jj = lane; jj < n; jj += 64) {
-      c1 += rowsum[F1.rsoff + (int64_t)jj * m + k];  // row k of every F1 slab
-      t2 += rowsum[F2.rsoff + (int64_t)k * n + jj];  // all rows of F2 slab k
+      t2 += rowsum[F2.rsoff + (int64_t)k * n + l];  // row k of the F2 row sums
     }
     s3 = wave_sum(s3);
-    c1 = wave_sum(c1);
     t2 = wave_sum(t2);
-    // sum_j R1[j][k] = -sum_j (rs1[j][k] - C_m(k)) + sum_j (rs2[k][j] - C_n(j))
-    const double sp = -c1 + (double)n * cost_rowsum(m, k) + t2 - cost_total(n) + s3;
     if (lane == 0) {
       vec[vec_PR3(G) + k] = s3;
-      vec[vec_Sp(G) + k] = sp;
+      vec[vec_tot2(G) + k] = t2;
     }
     p_sp = s3;
-    p_u = sp * dinv(m, k);
+    p_u = ((t2 - cost_total(n)) + s3) * dinv(m, k);
   }
   if (lane == 0) {
     wred[wave][0] = p_sa;
@@ -489,9 +515,21 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
 }
 
 // ---------------------------------------------------------------------------
-// Decision after a pass (identical in every solve block of the pair).
+// Decision after a pass (taken by one wave of every solve block of the pair,
+// on identical data, so all blocks agree).
 // ---------------------------------------------------------------------------
-__device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, PairCtl& nx,
+// KKT partials of a pair reduced by one wave (fixed lane-strided order, then a
+// butterfly); every lane returns the totals.
+__device__ inline void reduce_kpart(const PairGeo& G, const double* vec, int lane, double* acc) {
+  const double* kp = vec + vec_kpart(G);
+  for (int q = 0; q < 8; ++q) {
+    double v = 0.0;
+    for (int b = lane; b < G.nblk; b += 64) v += kp[(int64_t)b * kKP + q];
+    acc[q] = wave_sum(v);
+  }
+}
+
+__device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, PairCtl& nx,
                        bool& solve) {
   nx = c;
   solve = false;
@@ -518,11 +556,6 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, Pa
       solve = true;
       break;
     case MODE_CHECK: {
-      double acc[8];
-      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-      const double* kp = vec + vec_kpart(G);
-      for (int b = 0; b < G.nblk; ++b)
-        for (int q = 0; q < 8; ++q) acc[q] += kp[(int64_t)b * kKP + q];
       const double nx2 = sqrt(acc[KP_XX]), nz2 = sqrt(acc[KP_ZZ]);
       nx.res_d = sqrt(acc[KP_DUAL]) / (1.0 + G.norm_c);
       nx.res_c = sqrt(acc[KP_COMP]) / (1.0 + nx2 + nz2);
@@ -589,135 +622,228 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* vec, Pa
 //   y1^j = (I + 1 1^T / n)(Rhat1^j + Q t)/(m+n),  Q = I - e_m e_m^T / n,
 //   y2^j = (R2^j - (1^T y1^j) 1)/m,  1^T y1^j = 1^T (Rhat1^j + Q t) / n,
 //   y3^l = (R3^l + t)/n.
-// Every scalar is rebuilt from the reduce blocks' partials in a fixed order,
-// so each solve block needs no communication.  Wave w of block b writes the
-// alpha / beta of slab 4b + w (F1 slabs j first, then F2 slabs k).
+// The global scalars are rebuilt by one wave from the reduce blocks'
+// partials in a fixed order, so solve blocks need no communication.
+//   kind 0, row block b: wave w writes beta of slab 4b + w (F1 slabs j
+//           first, then F2 slabs k) and the slab's (sum alpha, sum beta);
+//   kind 1, tile (jt, kt): y1 on a 32 x 32 tile of (j, k), written as
+//           alpha of F1^(j) (row j) and, transposed through LDS, as
+//           -alpha of F2^(k) (row k).
+// FROM_R = 1 is the entry point that solves for a given R (the reduce side
+// then stores 1^T R1^j and sum_j R1[j][k] + PR3[k], and R1 itself).
 // ---------------------------------------------------------------------------
 struct SolveScalars {
   double sa, sp, u, sq, tlast;
 };
 
-__device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec) {
+template <int FROM_R>
+__device__ inline double b1_of(const PairGeo& G, const double* vec, int j) {
+  if (FROM_R) return vec[vec_b1(G) + j];
+  return -(vec[vec_tot1(G) + j] - cost_total(G.m)) +
+         (vec[vec_u2(G) + j] - (double)G.m * cost_rowsum(G.n, j));
+}
+
+template <int FROM_R>
+__device__ inline double Sp_of(const PairGeo& G, const double* vec, int k) {
+  if (FROM_R) return vec[vec_Sp(G) + k];
+  return -(vec[vec_u1(G) + k] - (double)G.n * cost_rowsum(G.m, k)) +
+         (vec[vec_tot2(G) + k] - cost_total(G.n)) + vec[vec_PR3(G) + k];
+}
+
+template <int FROM_R>
+__device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec, int lane) {
   const int m = G.m, n = G.n;
   const double dm = (double)m, dn = (double)n;
   const double* sp_ = vec + vec_spart(G);
   double sa = 0.0, sp = 0.0, up = 0.0;
-  for (int b = 0; b < G.nblk; ++b) {
+  for (int b = lane; b < G.nblk + G.ns1; b += 64) {
     sa += sp_[4 * (int64_t)b];
     sp += sp_[4 * (int64_t)b + 1];
     up += sp_[4 * (int64_t)b + 2];
   }
+  sa = wave_sum(sa);
+  sp = wave_sum(sp);
+  up = wave_sum(up);
   const double sdinv = (dm - 1.0) / dm + 1.0 / (dm + 1.0);
   SolveScalars S;
   S.sa = sa;
   S.sp = sp;
   S.u = up - (sa / dm) * sdinv;  // 1^T D^{-1} S
-  const double Sl = vec[vec_Sp(G) + m - 1] - sa / dm;
+  const double Sl = Sp_of<FROM_R>(G, vec, m - 1) - sa / dm;
   S.tlast = Sl / (dm + 1.0) + dm * (dm + 1.0) * S.u / (dm + 1.0);
   const double tsum = S.u * (1.0 + dm * (dm + 1.0) * sdinv);
   S.sq = tsum - S.tlast / dn;  // 1^T Q t
   return S;
 }
 
+template <int FROM_R>
 __device__ inline double t_entry(const PairGeo& G, const double* vec, const SolveScalars& S,
                                  int k) {
   const double dm = (double)G.m;
   const double d = dinv(G.m, k);
-  return (vec[vec_Sp(G) + k] - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
+  return (Sp_of<FROM_R>(G, vec, k) - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
 }
 
-__device__ inline double y1_entry(const PairGeo& G, const double* R1, const double* vec,
-                                  const SolveScalars& S, double qtk, int j, int k) {
-  const int m = G.m, n = G.n;
-  const double dm = (double)m, dn = (double)n;
-  const double aj = vec[vec_a(G) + j];
-  const double rsj = vec[vec_b1(G) + j] - aj + S.sp / dn + S.sq;  // 1^T (Rhat1^j + Q t)
-  const double rh = R1[(int64_t)j * m + k] - aj / dm + vec[vec_PR3(G) + k] / dn;
-  return (rh + qtk + rsj / dn) / (dm + dn);
+// 1^T (Rhat1^j + Q t)
+template <int FROM_R>
+__device__ inline double rs_of(const PairGeo& G, const double* vec, const SolveScalars& S, int j) {
+  return b1_of<FROM_R>(G, vec, j) - vec[vec_a(G) + j] + S.sp / (double)G.n + S.sq;
 }
 
-__device__ void solve_slab(const PairGeo& G, int slab, const double* arr, const double* vec,
+// beta of one slab, and the slab's (sum alpha, sum beta): sum_k y1[j][k] =
+// rs_j / n and sum_j y1[j][k] = t[k] in closed form.
+template <int FROM_R>
+__device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const double* vec,
                            double* ab, const SolveScalars& S, int lane) {
   const int m = G.m, n = G.n;
   const double dm = (double)m, dn = (double)n;
-  const double* R1 = arr + arr_R1(G);
-  if (slab < n) {  // F1^(j): alpha = y1[j][.], beta = y2[j][.]
+  if (slab < n) {  // F1^(j): beta = y2[j][.]
     const int j = slab;
     const double* R2 = arr + arr_R2(G);
     const FamGeo F = G.f[0];
-    double* al = ab + F.aboff + (int64_t)j * 2 * m;
-    double* be = al + m;
-    const double aj = vec[vec_a(G) + j];
-    const double rsj = vec[vec_b1(G) + j] - aj + S.sp / dn + S.sq;
-    double sa = 0.0, sb = 0.0;
-    for (int k = lane; k < m; k += 64) {
-      const double tk = t_entry(G, vec, S, k);
-      const double qtk = (k == m - 1) ? tk - tk / dn : tk;
-      const double v = y1_entry(G, R1, vec, S, qtk, j, k);
-      al[k] = v;
-      sa += v;
-    }
+    double* be = ab + F.aboff + (int64_t)j * 2 * m + m;
+    const double rsj = rs_of<FROM_R>(G, vec, S, j);
+    double sb = 0.0;
     for (int i = lane; i < m; i += 64) {
       const double v = (R2[(int64_t)j * m + i] - rsj / dn) / dm;
       be[i] = v;
       sb += v;
     }
-    sa = wave_sum(sa);
     sb = wave_sum(sb);
     if (lane == 0) {
-      ab[F.sumoff + 2 * (int64_t)j] = sa;
+      ab[F.sumoff + 2 * (int64_t)j] = rsj / dn;
       ab[F.sumoff + 2 * (int64_t)j + 1] = sb;
     }
-  } else if (slab < n + m) {  // F2^(k): alpha = -y1[.][k], beta = y3[.][k]
+  } else if (slab < n + m) {  // F2^(k): beta = y3[.][k]
     const int k = slab - n;
     const double* R3T = arr + arr_R3T(G);
     const FamGeo F = G.f[1];
-    double* al = ab + F.aboff + (int64_t)k * 2 * n;
-    double* be = al + n;
-    const double tk = t_entry(G, vec, S, k);
-    const double qtk = (k == m - 1) ? tk - tk / dn : tk;
-    double sa = 0.0, sb = 0.0;
-    for (int j = lane; j < n; j += 64) {
-      const double v = -y1_entry(G, R1, vec, S, qtk, j, k);
-      al[j] = v;
-      sa += v;
-    }
+    double* be = ab + F.aboff + (int64_t)k * 2 * n + n;
+    const double tk = t_entry<FROM_R>(G, vec, S, k);
+    double sb = 0.0;
     for (int l = lane; l < n; l += 64) {
       const double v = (k == m - 1 && l == n - 1) ? 0.0 : (R3T[(int64_t)k * n + l] + tk) / dn;
       be[l] = v;
       sb += v;
     }
-    sa = wave_sum(sa);
     sb = wave_sum(sb);
     if (lane == 0) {
-      ab[F.sumoff + 2 * (int64_t)k] = sa;
+      ab[F.sumoff + 2 * (int64_t)k] = -tk;
       ab[F.sumoff + 2 * (int64_t)k + 1] = sb;
     }
   }
 }
 
+// y1 on a 32 x 32 tile.  R1[j][k] comes from the two row-sum arrays (or is
+// read directly for FROM_R).
+template <int FROM_R>
+__device__ void solve_alpha_tile(const PairGeo& G, int tile, const double* rowsum,
+                                 const double* arr, const double* vec, double* ab,
+                                 const SolveScalars& S) {
+  __shared__ double T1[32][33], T2[32][33], Y[32][33];
+  __shared__ double s_rs[32], s_a[32], s_cn[32], s_qt[32], s_p3[32], s_cm[32];
+  const int m = G.m, n = G.n;
+  const double dm = (double)m, dn = (double)n;
+  const int jt = tile % G.ntj, kt = tile / G.ntj;
+  const int j0 = 32 * jt, k0 = 32 * kt;
+  const int t = threadIdx.x;
+  const FamGeo F1 = G.f[0], F2 = G.f[1];
+  if (t < 32) {
+    const int j = j0 + t;
+    if (j < n) {
+      s_rs[t] = rs_of<FROM_R>(G, vec, S, j);
+      s_a[t] = vec[vec_a(G) + j];
+      s_cn[t] = cost_rowsum(n, j);
+    }
+  } else if (t < 64) {
+    const int kk = t - 32, k = k0 + kk;
+    if (k < m) {
+      const double tk = t_entry<FROM_R>(G, vec, S, k);
+      s_qt[kk] = (k == m - 1) ? tk - tk / dn : tk;
+      s_p3[kk] = vec[vec_PR3(G) + k];
+      s_cm[kk] = cost_rowsum(m, k);
+    }
+  }
+  const double* rs1 = rowsum + F1.rsoff;  // [n][m]
+  const double* rs2 = rowsum + F2.rsoff;  // [m][n]
+  const double* R1 = arr + arr_R1(G);
+  for (int e = t; e < 1024; e += kWG) {
+    const int r = e >> 5, c = e & 31;
+    const int j = j0 + r, k = k0 + c;        // T1[r][c] = (j, k)
+    T1[r][c] = (j < n && k < m) ? (FROM_R ? R1[(int64_t)j * m + k] : rs1[(int64_t)j * m + k]) : 0.0;
+    if (!FROM_R) {
+      const int k2 = k0 + r, j2 = j0 + c;    // T2[r][c] = rs2[k2][j2]
+      T2[r][c] = (k2 < m && j2 < n) ? rs2[(int64_t)k2 * n + j2] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < 1024; e += kWG) {
+    const int jj = e >> 5, kk = e & 31;
+    const int j = j0 + jj, k = k0 + kk;
+    if (j < n && k < m) {
+      const double r1 =
+          FROM_R ? T1[jj][kk] : -(T1[jj][kk] - s_cm[kk]) + (T2[kk][jj] - s_cn[jj]);
+      const double rh = r1 - s_a[jj] / dm + s_p3[kk] / dn;
+      const double y = (rh + s_qt[kk] + s_rs[jj] / dn) / (dm + dn);
+      ab[F1.aboff + (int64_t)j * 2 * m + k] = y;
+      Y[jj][kk] = y;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < 1024; e += kWG) {
+    const int kk = e >> 5, jj = e & 31;
+    const int j = j0 + jj, k = k0 + kk;
+    if (j < n && k < m) ab[F2.aboff + (int64_t)k * 2 * n + j] = -Y[jj][kk];
+  }
+}
+
+template <int FROM_R>
 __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ sblocks,
                                                     const PairGeo* __restrict__ geo,
                                                     const PairCtl* __restrict__ ctl,
                                                     PairCtl* __restrict__ ctl_next,
+                                                    const double* __restrict__ rowsum,
                                                     const double* __restrict__ arr,
                                                     const double* __restrict__ vec,
                                                     double* __restrict__ ab) {
+  __shared__ PairCtl s_nx;
+  __shared__ SolveScalars s_S;
+  __shared__ int s_solve;
   const PBlock pbk = sblocks[blockIdx.x];
-  const PairCtl c = ctl[pbk.pair];
-  if (c.status != ST_RUNNING || c.mode == MODE_IDLE) {
-    if (pbk.blk == 0 && threadIdx.x == 0) ctl_next[pbk.pair] = c;
-    return;
+  const bool head = (pbk.kind == 0 && pbk.blk == 0 && threadIdx.x == 0);
+  if (!FROM_R) {
+    const PairCtl* cp = ctl + pbk.pair;
+    if (cp->status != ST_RUNNING || cp->mode == MODE_IDLE) {
+      if (head) ctl_next[pbk.pair] = *cp;
+      return;
+    }
   }
   const PairGeo G = geo[pbk.pair];
-  PairCtl nx;
-  bool solve;
-  decide(G, c, vec, nx, solve);
-  if (solve) {
-    const SolveScalars S = solve_scalars(G, vec);
-    solve_slab(G, 4 * pbk.blk + (threadIdx.x >> 6), arr, vec, ab, S, threadIdx.x & 63);
+  if (threadIdx.x < 64) {  // wave 0 decides and rebuilds the solve scalars
+    bool solve = true;
+    PairCtl nx;
+    if (!FROM_R) {
+      const PairCtl c = ctl[pbk.pair];
+      double acc[8];
+      if (c.mode == MODE_CHECK) reduce_kpart(G, vec, threadIdx.x, acc);
+      decide(G, c, acc, nx, solve);
+    }
+    SolveScalars S;
+    if (solve) S = solve_scalars<FROM_R>(G, vec, threadIdx.x);
+    if (threadIdx.x == 0) {
+      if (!FROM_R) s_nx = nx;
+      s_solve = solve ? 1 : 0;
+      if (solve) s_S = S;
+    }
   }
-  if (pbk.blk == 0 && threadIdx.x == 0) ctl_next[pbk.pair] = nx;
+  __syncthreads();
+  if (s_solve) {
+    if (pbk.kind == 0)
+      solve_beta<FROM_R>(G, 4 * pbk.blk + (threadIdx.x >> 6), arr, vec, ab, s_S, threadIdx.x & 63);
+    else
+      solve_alpha_tile<FROM_R>(G, pbk.blk, rowsum, arr, vec, ab, s_S);
+  }
+  if (!FROM_R && head) ctl_next[pbk.pair] = s_nx;
 }
 
 // ---------------------------------------------------------------------------
@@ -851,8 +977,8 @@ __global__ void k_scatter_R(const PairGeo* __restrict__ geo, int pair, const dou
   }
 }
 
-// Row totals of the solve from stored R arrays (hot_aat_solve path): the
-// same quantities k_pair_reduce produces from slab sums.
+// Totals of the solve from stored R arrays (entry point with R given): the
+// quantities k_pair_reduce produces from slab sums, taken from R directly.
 __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restrict__ blocks,
                                                           const PairGeo* __restrict__ geo,
                                                           const double* __restrict__ arr,
@@ -862,6 +988,10 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
   const PairGeo G = geo[pbk.pair];
   const int m = G.m, n = G.n, b = pbk.blk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (pbk.kind != 0) {  // strip slots carry no partial on this path
+    if (pbk.kind == 1 && threadIdx.x < 4) vec[vec_spart(G) + 4 * (int64_t)(G.nblk + b) + threadIdx.x] = 0.0;
+    return;
+  }
   const double* R1 = arr + arr_R1(G);
   const double* R2 = arr + arr_R2(G);
   const double* R3T = arr + arr_R3T(G);
@@ -904,17 +1034,6 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_pair_solve_only(const PBlock* __restrict__ sblocks,
-                                                         const PairGeo* __restrict__ geo,
-                                                         const double* __restrict__ arr,
-                                                         const double* __restrict__ vec,
-                                                         double* __restrict__ ab) {
-  const PBlock pbk = sblocks[blockIdx.x];
-  const PairGeo G = geo[pbk.pair];
-  const SolveScalars S = solve_scalars(G, vec);
-  solve_slab(G, 4 * pbk.blk + (threadIdx.x >> 6), arr, vec, ab, S, threadIdx.x & 63);
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers (C++ linkage inside the library).
 // ---------------------------------------------------------------------------
@@ -953,8 +1072,8 @@ void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
                      a.colpart[1 - par], a.kitem, a.ab, a.arr, a.vec);
-  hipLaunchKernelGGL(k_pair_solve, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
-                     a.ctl[par], a.ctl[1 - par], a.arr, a.vec, a.ab);
+  hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
+                     a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
 }
 
 // One iteration: slab pass, pair reduce, pair solve.  Reads ctl[par], writes ctl[1-par].
@@ -963,8 +1082,8 @@ void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
                      a.colpart[1 - par], a.kitem, a.ab, a.arr, a.vec);
-  hipLaunchKernelGGL(k_pair_solve, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
-                     a.ctl[par], a.ctl[1 - par], a.arr, a.vec, a.ab);
+  hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
+                     a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
 }
 
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
@@ -1003,8 +1122,9 @@ void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
   hipLaunchKernelGGL(k_scatter_R, dim3(grid), dim3(kWG), 0, st, a.geo, pair, R, a.arr);
   hipLaunchKernelGGL(k_pair_sums_from_R, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.arr, a.vec);
-  hipLaunchKernelGGL(k_pair_solve_only, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
-                     a.arr, a.vec, a.ab);
+  hipLaunchKernelGGL(k_pair_solve<1>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
+                     (const PairCtl*)nullptr, (PairCtl*)nullptr, (const double*)nullptr, a.arr,
+                     a.vec, a.ab);
 }
 
 }  // namespace hot

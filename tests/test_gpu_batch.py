@@ -1,0 +1,91 @@
+"""Batched solves: each problem's result is bit-identical alone and inside a
+batch of uneven sizes (same kernels, fixed reduction order), and matches the
+oracle to the FP64 tolerance.  Invalid inputs come back as HOT_E_INVALID."""
+import numpy as np
+import pytest
+
+from gpu_helpers import ctx, dev, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_batch_equals_alone_bitwise():
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    pairs = workloads.batch_pairs(12, sides=(8, 12, 16, 24))
+    c = ctx()
+    dp = [(dev(a), dev(b)) for a, b in pairs]
+    for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
+        batch = c.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec)
+        for (a, b), rb in zip(dp, batch):
+            ra, _ = c.solve(a, b, tol=1e-5, max_iter=200000, prec=prec)
+            for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
+                assert ra[key] == rb[key], (key, ra[key], rb[key])
+
+
+def test_batch_matches_oracle(oracle):
+    need_gpu()
+    from paper_2408_00598_amd import workloads
+    pairs = workloads.batch_pairs(6, sides=(6, 10, 14))
+    c = ctx()
+    res = c.batch_solve([(dev(a), dev(b)) for a, b in pairs], tol=1e-6, max_iter=200000)
+    for (a, b), r in zip(pairs, res):
+        _, _, _, _, o = oracle.hot(a, b, tol=1e-6, max_iter=200000)
+        assert r["status"] == 0 and o["converged"] == 1
+        assert r["iters"] == o["iters"]
+        assert abs(r["primal_obj"] - o["primal_obj"]) <= 1e-6 * abs(o["primal_obj"])
+
+
+def test_rectangular_and_degenerate_shapes(oracle):
+    need_gpu()
+    rng = np.random.default_rng(5)
+    c = ctx()
+    for m, n in [(1, 1), (1, 2), (2, 1), (3, 17), (17, 3), (4, 64)]:
+        mu1 = rng.uniform(0.1, 1, (m, n)); mu1 /= mu1.sum()
+        mu2 = rng.uniform(0.1, 1, (m, n)); mu2 /= mu2.sum()
+        r, _ = c.solve(dev(mu1), dev(mu2), tol=1e-7, max_iter=400000)
+        _, _, _, _, o = oracle.hot(mu1, mu2, tol=1e-7, max_iter=400000)
+        assert r["status"] == 0 and o["converged"] == 1
+        assert abs(r["primal_obj"] - o["primal_obj"]) <= 1e-6 * max(abs(o["primal_obj"]), 1e-9)
+
+
+def test_invalid_inputs_rejected():
+    need_gpu()
+    from paper_2408_00598_amd import hot
+    c = ctx()
+    good = np.full((4, 4), 1 / 16)
+    bad_neg = good.copy(); bad_neg[0, 0] = -1e-3; bad_neg[0, 1] += 1e-3
+    bad_nan = good.copy(); bad_nan[1, 1] = np.nan
+    bad_mass = good * 1.01
+    for bad in (bad_neg, bad_nan, bad_mass):
+        r, _ = c.solve(dev(good), dev(bad), tol=1e-6, raise_on_error=False)
+        assert r["return_status"] == hot.HOT_E_INVALID
+        assert c.last_error()
+    r, _ = c.solve(dev(good), dev(good), tol=0.0, raise_on_error=False)
+    assert r["return_status"] == hot.HOT_E_INVALID
+    r, _ = c.solve(dev(good), dev(good), tol=1e-6, max_iter=0, raise_on_error=False)
+    assert r["return_status"] == hot.HOT_E_INVALID
+
+
+def test_not_converged_reports_last_iterate():
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    mu1, mu2 = workloads.pair_small()
+    c = ctx()
+    r, _ = c.solve(dev(mu1), dev(mu2), tol=1e-9, max_iter=35, raise_on_error=False)
+    assert r["return_status"] == hot.HOT_E_NOT_CONVERGED
+    assert r["iters"] == 35 and r["kkt"] > 1e-9 and np.isfinite(r["primal_obj"])
+
+
+def test_zero_mass_bins(oracle):
+    need_gpu()
+    from paper_2408_00598_amd import workloads
+    rng = np.random.default_rng(workloads.seed_for(0, 777))
+    mu1, mu2 = workloads.masked_shape(16, 16, rng), workloads.masked_shape(16, 16, rng)
+    c = ctx()
+    r, sol = c.solve(dev(mu1), dev(mu2), keep=True, tol=1e-6)
+    _, _, _, _, o = oracle.hot(mu1, mu2, tol=1e-6)
+    assert r["status"] == 0
+    assert abs(r["primal_obj"] - o["primal_obj"]) <= 1e-6 * abs(o["primal_obj"])
+    src, dst, mass, err = sol.recover_plan()
+    assert err[2] <= 1e-12 and err[3] <= 1e-12
