@@ -170,6 +170,40 @@ hot_status hot_batch_submit(hot_ctx *ctx, const hot_problem *probs,
                             hot_batch **out);
 hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
 
+/* Continuous-batching service.  A worker thread admits queued problems
+ * (FIFO) whenever fewer than max_slots are resident and the sum of their
+ * device footprints (hot_footprint_bytes) stays within hbm_budget_bytes
+ * (0: 80% of the free device memory at creation).  Each resident problem is
+ * iterated on its own stream by its captured graph, so problems admitted at
+ * different times run concurrently; iterates stay on the device until the
+ * problem stops.  A problem's result equals its hot_solve result.
+ * submit: non-blocking; the histograms must stay valid until its result has
+ *   been polled.  HOT_E_INVALID for a malformed problem (histogram values are
+ *   validated at admission and reported in the result status), HOT_E_NOMEM
+ *   if its footprint alone exceeds the budget.
+ * poll: copies up to max finished results (each returned once) with their
+ *   tags and latency (submit to completion, seconds); returns how many.
+ * drain: waits until every submitted problem has finished (HOT_E_BUSY on
+ *   timeout).
+ * stats: out[8] = completed, submitted, queued, resident, bytes resident,
+ *   most resident at once, p50 latency, p99 latency (seconds).
+ * destroy: drops queued problems, waits for resident ones, frees all. */
+typedef struct {
+  size_t hbm_budget_bytes;
+  int32_t max_slots; /* 1..1024 */
+  int32_t reserved;
+} hot_server_config;
+
+hot_status hot_server_create(hot_ctx *ctx, const hot_server_config *cfg,
+                             hot_server **out);
+hot_status hot_server_submit(hot_server *srv, const hot_problem *prob,
+                             uint64_t tag);
+int32_t hot_server_poll(hot_server *srv, hot_result *results, uint64_t *tags,
+                        double *latency_s, int32_t max);
+hot_status hot_server_drain(hot_server *srv, double timeout_s);
+hot_status hot_server_stats(hot_server *srv, double *out);
+void hot_server_destroy(hot_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

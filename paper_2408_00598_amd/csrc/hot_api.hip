@@ -205,6 +205,8 @@ namespace hot {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
+  if (quantum_event) (void)hipEventDestroy(quantum_event);
+  quantum_event = nullptr;
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
   graph_exec = nullptr;
@@ -516,6 +518,32 @@ hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_gra
   }
   for (auto& e : evs) (void)hipEventDestroy(e);
   return result;
+}
+
+hot_status Workspace::ensure_graph(hot_ctx* ctx, hipStream_t st) {
+  if (graph_exec) return HOT_OK;
+  HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < kGraphIters; ++i) launch_iteration(args, i & 1, st);
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (e != hipSuccess) {
+    if (ctx) ctx->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+    return HOT_E_DEVICE;
+  }
+  HIPCK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+  return HOT_OK;
+}
+
+hipError_t Workspace::launch_quantum(hipStream_t st) {
+  hipError_t e;
+  if (!quantum_event) {
+    e = hipEventCreateWithFlags(&quantum_event, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  e = hipGraphLaunch(graph_exec, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(host_ctl, ctl_d, lay.geo.size() * sizeof(PairCtl), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(quantum_event, st);
 }
 
 static hot_status status_of(int32_t s) {

@@ -97,6 +97,11 @@ struct Workspace {
   hot_status alloc_all(hot_ctx* ctx);
   hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
   hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
+  // Non-blocking pieces of run() for the server: capture the graph once,
+  // launch one graph (kGraphIters iterations) + status copy + event.
+  hot_status ensure_graph(hot_ctx* ctx, hipStream_t st);
+  hipError_t launch_quantum(hipStream_t st);
+  hipEvent_t quantum_event = nullptr;
   hot_status run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
   void fill_result(int p, hot_result* r, double seconds) const;
 };

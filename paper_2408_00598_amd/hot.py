@@ -24,8 +24,14 @@ EXPORTED = [
     "hot_footprint_bytes", "hot_plan_capacity", "hot_solve", "hot_solution_export",
     "hot_solution_free", "hot_recover_plan", "hot_aat_solve", "hot_batch_submit",
     "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
-    "hot_server_stats", "hot_server_destroy", "hot_ctx_set_profiling", "hot_ctx_profile_read",
+    "hot_server_stats", "hot_server_destroy", "hot_server_drain", "hot_ctx_set_profiling",
+    "hot_ctx_profile_read",
 ]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -78,6 +84,14 @@ def lib():
     L.hot_aat_solve.argtypes = [vp, i32, i32, vp, vp, vp]
     L.hot_batch_submit.argtypes = [vp, C.POINTER(Problem), i32, vp, C.POINTER(vp)]
     L.hot_batch_wait.argtypes = [vp, C.POINTER(Result)]
+    L.hot_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+    L.hot_server_submit.argtypes = [vp, C.POINTER(Problem), C.c_uint64]
+    L.hot_server_poll.argtypes = [vp, C.POINTER(Result), C.POINTER(C.c_uint64),
+                                  C.POINTER(dbl), i32]
+    L.hot_server_poll.restype = i32
+    L.hot_server_drain.argtypes = [vp, dbl]
+    L.hot_server_stats.argtypes = [vp, C.POINTER(dbl)]
+    L.hot_server_destroy.argtypes = [vp]
     L.hot_ctx_set_profiling.argtypes = [vp, C.c_int]
     L.hot_ctx_profile_read.argtypes = [vp, C.POINTER(dbl)]
     if hasattr(L, "hot_recover_plan"):
@@ -88,6 +102,8 @@ def lib():
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.hot_ctx_destroy.restype = None
     L.hot_solution_free.restype = None
+    L.hot_server_destroy.restype = None
+    L.hot_server_poll.restype = i32
     _lib = L
     return L
 
@@ -268,3 +284,58 @@ class Solution:
             raise HotError(st, self.ctx.last_error())
         k = nnz.value
         return src[:k], dst[:k], mass[:k], list(err)
+
+
+class Server:
+    """Continuous-batching service on one context (hot_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 8):
+        self.ctx = ctx
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, 0)
+        h = C.c_void_p()
+        st = lib().hot_server_create(ctx.h, C.byref(cfg), C.byref(h))
+        if st != HOT_OK:
+            raise HotError(st, ctx.last_error())
+        self.h = h
+        self._alive = {}
+
+    def submit(self, mu1, mu2, tag: int, **kw):
+        prob = self.ctx.problem(mu1, mu2, **kw)
+        st = lib().hot_server_submit(self.h, C.byref(prob), tag)
+        if st != HOT_OK:
+            raise HotError(st, "submit rejected")
+        self._alive[tag] = (mu1, mu2)
+
+    def poll(self, max_results: int = 256):
+        res = (Result * max_results)()
+        tags = (C.c_uint64 * max_results)()
+        lat = (C.c_double * max_results)()
+        k = lib().hot_server_poll(self.h, res, tags, lat, max_results)
+        out = []
+        for q in range(k):
+            d = res[q].as_dict()
+            d["tag"], d["latency"] = int(tags[q]), float(lat[q])
+            self._alive.pop(d["tag"], None)
+            out.append(d)
+        return out
+
+    def drain(self, timeout: float = 600.0):
+        return lib().hot_server_drain(self.h, timeout)
+
+    def stats(self):
+        out = (C.c_double * 8)()
+        lib().hot_server_stats(self.h, out)
+        keys = ["completed", "submitted", "queued", "resident", "bytes_resident",
+                "max_resident", "p50", "p99"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hot_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

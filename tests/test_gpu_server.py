@@ -1,0 +1,66 @@
+"""Continuous-batching service: problems submitted while others are resident
+are admitted as slots and HBM budget free up, run concurrently, and each
+result is identical to the same problem solved alone."""
+import time
+
+import numpy as np
+import pytest
+
+from gpu_helpers import ctx, dev, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_server_results_equal_alone_and_overlap():
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    c = ctx()
+    srv = hot.Server(c, hbm_budget_bytes=0, max_slots=3)
+    reqs = []
+    rng = np.random.default_rng(11)
+    for t in range(9):
+        n = (16, 24, 32)[t % 3]
+        a = workloads.gaussian_blobs(n, n, 2, rng)
+        b = workloads.gaussian_blobs(n, n, 3, rng)
+        tol = 1e-4 if t % 2 else 1e-6
+        prec = hot.HOT_FP32_STREAM if t % 4 == 1 else hot.HOT_FP64
+        reqs.append((t, dev(a), dev(b), tol, prec))
+    for q, (t, a, b, tol, prec) in enumerate(reqs):
+        srv.submit(a, b, t, tol=tol, prec=prec, max_iter=200000)
+        if q in (2, 5):
+            time.sleep(0.01)  # later arrivals join a running mix
+    assert srv.drain(300.0) == hot.HOT_OK
+    got = {r["tag"]: r for r in srv.poll(64)}
+    st = srv.stats()
+    srv.close()
+    assert len(got) == len(reqs)
+    assert st["max_resident"] >= 2 and st["max_resident"] <= 3
+    assert st["p99"] >= st["p50"] > 0
+    for t, a, b, tol, prec in reqs:
+        alone, _ = c.solve(a, b, tol=tol, prec=prec, max_iter=200000)
+        r = got[t]
+        for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
+            assert r[key] == alone[key], (t, key, r[key], alone[key])
+
+
+def test_server_admission_respects_budget():
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    c = ctx()
+    fp = hot.footprint_bytes(32, 32, hot.HOT_FP64)
+    srv = hot.Server(c, hbm_budget_bytes=int(2.5 * fp), max_slots=8)
+    pairs = [workloads.pair_small(p) for p in range(5)]
+    keep = [(dev(a), dev(b)) for a, b in pairs]
+    for t, (a, b) in enumerate(keep):
+        srv.submit(a, b, t, tol=1e-5, max_iter=200000)
+    assert srv.drain(300.0) == hot.HOT_OK
+    res = srv.poll(16)
+    st = srv.stats()
+    srv.close()
+    assert len(res) == 5 and all(r["status"] == 0 for r in res)
+    assert st["max_resident"] == 2
+    # a problem larger than the whole budget is refused at submission
+    srv = hot.Server(c, hbm_budget_bytes=fp // 2, max_slots=2)
+    with pytest.raises(hot.HotError):
+        srv.submit(*keep[0], 99, tol=1e-5)
+    srv.close()
