@@ -13,6 +13,9 @@ Workloads (named by what they are):
   pair128   one 128 x 128 pair (5 blobs), FP32 streams, rel KKT 1e-4
   pair512   one 512 x 512 pair (1-8 blobs + Cauchy blob), FP32, rel KKT 1e-4
   small     one 32 x 32 pair (3 blobs), FP64, rel KKT 1e-6
+  serving   Poisson arrivals (200/s for --duration s), side in {64,96,128,192,256},
+            1-5 blob mixtures, tolerance 1e-4 (70%, FP32 streams) or 1e-6 (30%,
+            FP64), continuous batching; reports solves/s and p50/p99 latency
 
 Prints one JSON line.
 """
@@ -52,6 +55,88 @@ def make_workload(name, pairs):
     raise SystemExit(f"unknown workload {name}")
 
 
+def run_serving(args):
+    """Replay a Poisson trace against the continuous-batching server."""
+    import threading
+    import torch
+    from paper_2408_00598_amd import hot, workloads
+    trace = workloads.serving_trace(rate=args.rate, duration=args.duration)
+    dev = torch.device("cuda:0")
+    # a pool of distinct pairs per side, resident in HBM before the clock starts
+    pool = {}
+    for n in workloads.SERVE_SIDES:
+        pool[n] = []
+        for q in range(args.pool):
+            a, b = workloads.serving_pair(n, workloads.seed_for(4, 1000 * n + q))
+            pool[n].append((torch.tensor(a, device=dev), torch.tensor(b, device=dev)))
+    torch.cuda.synchronize()
+    ctx = hot.Context(0)
+    # warm the per-shape workspaces and graphs
+    srv = hot.Server(ctx, max_slots=args.slots)
+    for n in workloads.SERVE_SIDES:
+        for prec, tol in ((hot.HOT_FP32_STREAM, 1e-4), (hot.HOT_FP64, 1e-6)):
+            srv.submit(*pool[n][0], -1, tol=tol, prec=prec, max_iter=1000000)
+    srv.drain(600.0)
+    srv.poll(1024)
+    srv.close()
+    srv = hot.Server(ctx, max_slots=args.slots)
+    results = []
+    t0 = time.perf_counter()
+
+    def feeder():
+        for q, (t, n, tol, seed) in enumerate(trace):
+            now = time.perf_counter() - t0
+            if t > now:
+                time.sleep(t - now)
+            a, b = pool[n][seed % args.pool]
+            prec = hot.HOT_FP32_STREAM if tol >= 1e-4 else hot.HOT_FP64
+            srv.submit(a, b, q, tol=tol, prec=prec, max_iter=1000000)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    last = 0.0
+    deadline = None
+    while True:
+        results += srv.poll(4096)
+        now = time.perf_counter() - t0
+        st = srv.stats()
+        if now - last >= 1.0:
+            last = now
+            print(f"[serving] t={now:6.1f}s submitted={int(st['submitted'])} "
+                  f"completed={int(st['completed'])} queued={int(st['queued'])} "
+                  f"resident={int(st['resident'])}", file=sys.stderr, flush=True)
+        if not th.is_alive():
+            if deadline is None:
+                deadline = now + args.drain
+            if st["completed"] >= st["submitted"] or now >= deadline:
+                break
+        time.sleep(0.05)
+    th.join()
+    elapsed = time.perf_counter() - t0
+    results += srv.poll(1 << 20)
+    st = srv.stats()
+    srv.close()  # drops requests still queued, stops the resident ones
+    lat = np.array([r["latency"] for r in results])
+    iters = np.array([r["iters"] for r in results])
+    out = {
+        "metric": METRIC, "value": len(results) / elapsed, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": elapsed * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "stream_dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson {args.rate:g} req/s for {args.duration:g} s, "
+                               "n~U{64,96,128,192,256}, 1-5 Gaussian blobs, tol 1e-4 (70%, FP32 "
+                               "streams) / 1e-6 (30%, FP64), continuous batching",
+                   "requests": len(trace), "slots": args.slots},
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "offered_rate": args.rate, "completed": len(results),
+        "dropped_in_queue": int(st["queued"]), "stopped_resident": int(st["resident"]),
+        "drain_cap_s": args.drain,
+        "converged": int(sum(r["status"] == 0 for r in results)),
+        "max_resident": st["max_resident"], "iters_mean": float(iters.mean()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(pairs, results, tol, budget_s=20.0):
     """Oracle (FP64, single thread) seconds per iteration measured per grid
     side on the first pair of that side, times the iterations each pair took,
@@ -89,6 +174,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--plan", action="store_true", help="recover plans inside each step")
+    ap.add_argument("--duration", type=float, default=10.0, help="serving trace length (s)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving arrival rate (1/s)")
+    ap.add_argument("--slots", type=int, default=16, help="serving resident problems")
+    ap.add_argument("--drain", type=float, default=20.0,
+                    help="serving: seconds to keep draining after the last arrival")
+    ap.add_argument("--pool", type=int, default=8, help="serving distinct pairs per side")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) 5 times, for scaling "
                          "hardware byte counters")
@@ -96,6 +187,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "serving":
+        run_serving(args)
+        return
 
     import torch
     from paper_2408_00598_amd import hot

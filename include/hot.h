@@ -187,7 +187,8 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
  *   timeout).
  * stats: out[8] = completed, submitted, queued, resident, bytes resident,
  *   most resident at once, p50 latency, p99 latency (seconds).
- * destroy: drops queued problems, waits for resident ones, frees all. */
+ * destroy: drops queued problems, stops resident ones after their current
+ *   quantum (their results, not polled, are discarded), frees all. */
 typedef struct {
   size_t hbm_budget_bytes;
   int32_t max_slots; /* 1..1024 */

@@ -161,7 +161,8 @@ static void server_loop(hot_server* S) {
       }
       progressed = true;
       const bool running = (e == hipSuccess) && sl.ws->host_ctl[0].status == ST_RUNNING;
-      if (running && sl.quanta < sl.max_quanta) {
+      const bool cancel = S->stop.load();
+      if (running && !cancel && sl.quanta < sl.max_quanta) {
         if (sl.ws->launch_quantum(sl.ws->stream) == hipSuccess) {
           ++sl.quanta;
           ++q;
@@ -175,6 +176,7 @@ static void server_loop(hot_server* S) {
       const double t = now_s();
       sl.ws->fill_result(0, &d.res, t - sl.req.t_submit);
       if (e != hipSuccess) d.res.status = HOT_E_DEVICE;
+      else if (running) d.res.status = HOT_E_CANCELLED;
       d.tag = sl.req.tag;
       d.latency = t - sl.req.t_submit;
       {
@@ -304,7 +306,7 @@ void hot_server_destroy(hot_server* S) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->queue.clear();  // requests not yet admitted are dropped
   }
-  S->stop = true;
+  S->stop = true;  // resident problems stop after their current quantum
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
   delete S;
