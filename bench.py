@@ -137,6 +137,31 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def measured_traffic(workload):
+    """HBM traffic per slab-pass launch from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the current kernel source."""
+    import hashlib
+    name = {"batched": "slab_pass_batched256_fp32_traffic.md"}.get(workload)
+    if not name:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_2408_00598_amd", "csrc", "hot_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", "`")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"]) / 1e9
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(pairs, results, tol, budget_s=20.0):
     """Oracle (FP64, single thread) seconds per iteration measured per grid
     side on the first pair of that side, times the iterations each pair took,
@@ -229,8 +254,10 @@ def main():
     prof = ctx.profile()
     ctx.set_profiling(False)
     achieved = prof["slab_bytes"] / prof["slab_seconds"] / 1e9 if prof["slab_seconds"] else 0.0
+    traffic = measured_traffic(args.workload)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "frac": achieved / PEAK_HBM_GBS,
+                "traffic": traffic,  # GB per launch (rocprofv3 FETCH/WRITE, copy-calibrated)
                 "kernel": "k_slab_pass",
                 "launches": prof["slab_launches"],
                 "avg_launch_us": prof["slab_seconds"] / max(1, prof["slab_launches"]) * 1e6,
