@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--workload", default="batched")
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip tuning the slab-pass launch shape before the warmup")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--plan", action="store_true", help="recover plans inside each step")
     ap.add_argument("--duration", type=float, default=10.0, help="serving trace length (s)")
@@ -237,6 +239,9 @@ def main():
             return out
         return ctx.batch_solve(dpairs, **kw)
 
+    tuned = None
+    if not args.no_autotune:
+        tuned = ctx.autotune(dpairs, iters=30, prec=prec)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -271,6 +276,7 @@ def main():
         "dtype": "f64", "stream_dtype": "f32" if prec == hot.HOT_FP32_STREAM else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "pairs": len(dpairs), "tol": tol},
+        "autotune": tuned,
         "roofline": roofline,
         "solve_stats": {"iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
                         "kkt_max": float(max(r["kkt"] for r in results)),

@@ -111,6 +111,22 @@ const char *hot_status_string(hot_status s);
 hot_status hot_ctx_set_profiling(hot_ctx *ctx, int on);
 hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
 
+/* Autotuner of the slab-pass launch shape.  For the shapes and precision of
+ * probs (histogram values are ignored: uniform histograms are solved),
+ * times `iters` fixed iterations under each candidate workgroup size (2^11 ..
+ * 2^17 flow elements per workgroup) and row unroll (1, 2), with hipEvents
+ * around every slab pass, and keeps the fastest in ctx for launches of the
+ * same total size class and precision.  cache_path (nullable): the choice
+ * is appended as a JSON line keyed by device architecture, precision and
+ * size class; hot_autotune_load reads such a file (later lines win, entries
+ * of other architectures are ignored).  out (nullable, 4 doubles): chosen
+ * elements per workgroup, chosen unroll, its slab seconds per iteration, and
+ * the built-in rule's.  The chunking changes the summation order of column
+ * partial sums, so tuned results can differ from untuned ones by rounding. */
+hot_status hot_autotune(hot_ctx *ctx, const hot_problem *probs, int32_t count,
+                        int32_t iters, const char *cache_path, double *out);
+hot_status hot_autotune_load(hot_ctx *ctx, const char *cache_path);
+
 /* Device bytes one problem needs (state buffers, sums, dual vectors).
  * Pure host arithmetic; 0 for invalid sizes. */
 size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags);
@@ -163,8 +179,11 @@ hot_status hot_aat_solve(hot_ctx *ctx, int32_t m, int32_t n, const double *R,
 /* Batched solves: many problems (sizes may differ) share every launch; the
  * iteration loop runs device-side in captured HIP graphs.  Submit returns
  * once the work is enqueued and a host thread drives it; hot_batch_wait
- * blocks, fills results[count] and frees the handle.  Each problem's result
- * equals its hot_solve result (same kernels, same reduction order). */
+ * blocks, fills results[count] and frees the handle.  Each problem runs the
+ * same kernels and decisions as under hot_solve; the slab-pass chunking
+ * depends on the launch's total size, so a result is bit-identical to the
+ * solo one when the chunking coincides and otherwise differs only in the
+ * summation order of column partial sums (within rounding). */
 hot_status hot_batch_submit(hot_ctx *ctx, const hot_problem *probs,
                             int32_t count, hot_stream_t stream,
                             hot_batch **out);

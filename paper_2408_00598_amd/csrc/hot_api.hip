@@ -63,6 +63,23 @@ static double slab_cost_sq(int L) {
   return (double)s;
 }
 
+int size_class(int64_t pair_elems) {
+  int c = 0;
+  while ((int64_t(1) << (c + 1)) <= pair_elems) ++c;
+  return c;
+}
+
+int64_t Tuning::item_elems_for(int64_t pair_elems, int fp32) const {  // pair_elems: launch total
+  auto it = table.find({fp32, size_class(pair_elems)});
+  if (it != table.end()) return it->second.first;
+  return std::max<int64_t>(2048, std::min<int64_t>(item_elems, pair_elems / std::max<int64_t>(1, min_items)));
+}
+
+int Tuning::unroll_for(int64_t elems, int fp32) const {
+  auto it = table.find({fp32, size_class(elems)});
+  return it != table.end() ? it->second.second : unroll;
+}
+
 Tuning default_tuning() {
   Tuning t;
   t.item_elems = 65536;
@@ -91,12 +108,12 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       err = "grid sides must be in [1, " + std::to_string(kMaxSide) + "]";
       return false;
     }
-    total += (int64_t)n * m * round_up(m, W) + (int64_t)m * n * round_up(n, W);
+    total += (int64_t)m * m * n + (int64_t)m * n * n;
   }
   // workgroup size of the slab pass: enough workgroups to fill the chip,
-  // never more than item_elems elements each
-  const int64_t item_elems =
-      std::max<int64_t>(2048, std::min<int64_t>(tune.item_elems, total / std::max<int64_t>(1, tune.min_items)));
+  // never more than item_elems elements each (or the autotuned size for
+  // this total)
+  const int64_t item_elems = tune.item_elems_for(total, fp32);
   int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0;
   int maxvpl = 1;
   for (size_t p = 0; p < shapes.size(); ++p) {
@@ -692,7 +709,12 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
   ws->device = ctx->device;
   ws->profile = ctx->profiling;
   hot_status s = ws->alloc_all(ctx);
-  ws->args.unroll = ctx->tune.unroll;
+  {
+    int64_t total = 0;
+    for (int p = 0; p < count; ++p)
+      total += (int64_t)probs[p].m * probs[p].m * probs[p].n + (int64_t)probs[p].m * probs[p].n * probs[p].n;
+    ws->args.unroll = ctx->tune.unroll_for(total, prec == HOT_FP32_STREAM);
+  }
   ws->args.slab_grid = ws->args.nitems;
   if (s != HOT_OK) return s;
   if (hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking) != hipSuccess) {

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -18,10 +19,17 @@ constexpr int kGraphIters = 20;
 
 struct Tuning {
   int64_t item_elems;   // largest target of elements per slab-pass workgroup
-  int64_t min_items;    // aim for at least this many slab-pass workgroups
+  int64_t min_items;    // aim for at least this many slab-pass workgroups per launch
   int unroll;           // rows loaded ahead per wave (1 or 2)
+  // autotuned elements per workgroup, keyed by (precision, log2 of the
+  // launch's flow elements); overrides the rule above for that size class
+  std::map<std::pair<int, int>, std::pair<int64_t, int>> table;  // -> (elements, unroll)
+  // elements per slab-pass workgroup for a launch over `elems` flow elements
+  int64_t item_elems_for(int64_t elems, int fp32) const;
+  int unroll_for(int64_t elems, int fp32) const;
 };
 Tuning default_tuning();
+int size_class(int64_t pair_elems);
 
 struct LaunchArgs {
   const SlabItem* items = nullptr;

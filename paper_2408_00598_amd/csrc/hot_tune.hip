@@ -1,0 +1,152 @@
+// Autotuner of the slab-pass launch shape (hot_autotune, hot_autotune_load).
+//
+// For a set of problem shapes, every candidate workgroup size (elements per
+// slab-pass workgroup, 2^11 .. 2^17) and row unroll (1, 2) is timed on a fixed
+// number of iterations of uniform histograms with hipEvents around each slab
+// pass; the fastest is stored in the context for launches of that total size
+// and precision, and optionally appended to a JSON-lines cache file keyed by
+// device architecture, precision and size class.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hot.h"
+#include "hot_internal.h"
+#include "hot_runtime.h"
+
+using namespace hot;
+
+static std::string arch_name(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32_t count,
+                                   int32_t iters, const char* cache_path, double* out) {
+  if (!ctx || !probs || count < 1 || iters < 1) return HOT_E_INVALID;
+  if (hipSetDevice(ctx->device) != hipSuccess) return HOT_E_DEVICE;
+  const int prec = probs[0].prec;
+  // uniform histograms of every shape (values do not affect timing)
+  std::vector<hot_problem> pr(probs, probs + count);
+  std::vector<void*> bufs;
+  int64_t total = 0;
+  for (auto& p : pr) {
+    if (p.m < 1 || p.n < 1 || p.m > kMaxSide || p.n > kMaxSide || p.prec != prec) {
+      for (void* b : bufs) (void)hipFree(b);
+      ctx->err = "autotune: bad shapes or mixed precision";
+      return HOT_E_INVALID;
+    }
+    const int64_t M = (int64_t)p.m * p.n;
+    total += (int64_t)p.m * p.m * p.n + (int64_t)p.m * p.n * p.n;
+    std::vector<double> h((size_t)M, 1.0 / (double)M);
+    void* d = nullptr;
+    if (hipMalloc(&d, M * sizeof(double)) != hipSuccess ||
+        hipMemcpy(d, h.data(), M * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      for (void* b : bufs) (void)hipFree(b);
+      ctx->err = "autotune: allocation failed";
+      return HOT_E_NOMEM;
+    }
+    bufs.push_back(d);
+    p.mu1 = (const double*)d;
+    p.mu2 = (const double*)d;
+    p.tol = 1.0;
+    p.max_iter = iters;
+    p.check_every = 1 << 30;
+    p.flags = HOT_FLAG_FIXED_ITERS;
+  }
+  const int cls = size_class(total);
+  const std::pair<int, int> key{prec == HOT_FP32_STREAM, cls};
+  const Tuning saved = ctx->tune;
+  double best = 1e300, dflt = 0.0;
+  int64_t best_e = 0;
+  int best_u = 1;
+  hot_status status = HOT_OK;
+  std::vector<std::pair<int64_t, int>> cands;
+  cands.push_back({0, saved.unroll});  // the built-in rule first (reference)
+  for (int64_t e = 2048; e <= 131072; e *= 2)
+    for (int u = 1; u <= 2; ++u) cands.push_back({e, u});
+  for (size_t c = 0; c < cands.size() && status == HOT_OK; ++c) {
+    Tuning t = saved;
+    t.table.erase(key);
+    if (cands[c].first > 0) t.table[key] = cands[c];
+    else t.unroll = cands[c].second;
+    hot_ctx tmp;
+    tmp.device = ctx->device;
+    tmp.tune = t;
+    tmp.profiling = true;
+    std::shared_ptr<Workspace> ws;
+    double secs = 0.0;
+    for (int rep = 0; rep < 2 && status == HOT_OK; ++rep) {  // first run warms up
+      status = make_workspace(&tmp, pr.data(), count, ws);
+      if (status == HOT_OK) status = ws->setup(&tmp, pr.data(), count, ws->stream);
+      if (status == HOT_OK) status = ws->run(&tmp, ws->stream, (int64_t)iters * 2 / kGraphIters + 8);
+      if (status == HOT_OK) secs = ws->prof_seconds / (double)(iters + 1);
+    }
+    if (status != HOT_OK) {
+      ctx->err = "autotune: " + tmp.err;
+      break;
+    }
+    if (c == 0) dflt = secs;
+    if (c > 0 && secs < best) {
+      best = secs;
+      best_e = cands[c].first;
+      best_u = cands[c].second;
+    }
+  }
+  for (void* b : bufs) (void)hipFree(b);
+  if (status != HOT_OK) return status;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tune.table[key] = {best_e, best_u};
+  }
+  if (cache_path && cache_path[0]) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f,
+                   "{\"arch\": \"%s\", \"fp32\": %d, \"size_class\": %d, \"item_elems\": %lld, "
+                   "\"unroll\": %d, \"slab_us_per_iter\": %.3f, \"default_us_per_iter\": %.3f}\n",
+                   arch_name(ctx->device).c_str(), key.first, cls, (long long)best_e, best_u,
+                   best * 1e6, dflt * 1e6);
+      std::fclose(f);
+    }
+  }
+  if (out) {
+    out[0] = (double)best_e;
+    out[1] = (double)best_u;
+    out[2] = best;
+    out[3] = dflt;
+  }
+  return HOT_OK;
+}
+
+extern "C" hot_status hot_autotune_load(hot_ctx* ctx, const char* cache_path) {
+  if (!ctx || !cache_path) return HOT_E_INVALID;
+  FILE* f = std::fopen(cache_path, "r");
+  if (!f) return HOT_E_INVALID;
+  const std::string arch = arch_name(ctx->device);
+  char line[512];
+  int loaded = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    char a[64] = {0};
+    int fp32 = 0, cls = 0, u = 1;
+    long long e = 0;
+    if (std::sscanf(line,
+                    "{\"arch\": \"%63[^\"]\", \"fp32\": %d, \"size_class\": %d, \"item_elems\": "
+                    "%lld, \"unroll\": %d",
+                    a, &fp32, &cls, &e, &u) == 5 &&
+        arch == a && e >= 1024 && (u == 1 || u == 2)) {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->tune.table[{fp32, cls}] = {(int64_t)e, u};  // later lines win
+      ++loaded;
+    }
+  }
+  std::fclose(f);
+  return loaded > 0 ? HOT_OK : HOT_E_INVALID;
+}

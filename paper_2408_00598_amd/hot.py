@@ -25,7 +25,7 @@ EXPORTED = [
     "hot_solution_free", "hot_recover_plan", "hot_aat_solve", "hot_batch_submit",
     "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
     "hot_server_stats", "hot_server_destroy", "hot_server_drain", "hot_ctx_set_profiling",
-    "hot_ctx_profile_read",
+    "hot_ctx_profile_read", "hot_autotune", "hot_autotune_load",
 ]
 
 
@@ -92,6 +92,8 @@ def lib():
     L.hot_server_drain.argtypes = [vp, dbl]
     L.hot_server_stats.argtypes = [vp, C.POINTER(dbl)]
     L.hot_server_destroy.argtypes = [vp]
+    L.hot_autotune.argtypes = [vp, C.POINTER(Problem), i32, i32, C.c_char_p, C.POINTER(dbl)]
+    L.hot_autotune_load.argtypes = [vp, C.c_char_p]
     L.hot_ctx_set_profiling.argtypes = [vp, C.c_int]
     L.hot_ctx_profile_read.argtypes = [vp, C.POINTER(dbl)]
     if hasattr(L, "hot_recover_plan"):
@@ -204,6 +206,20 @@ class Context:
         if st != HOT_OK:
             raise HotError(st, self.last_error())
         return y
+
+    def autotune(self, pairs, iters=40, cache_path=None, **kw):
+        """Tune the slab-pass launch shape for these shapes / precision."""
+        probs = (Problem * len(pairs))(*[self.problem(a, b, **kw) for a, b in pairs])
+        out = (C.c_double * 4)()
+        st = lib().hot_autotune(self.h, probs, len(pairs), iters,
+                                cache_path.encode() if cache_path else None, out)
+        if st != HOT_OK:
+            raise HotError(st, self.last_error())
+        return {"item_elems": int(out[0]), "unroll": int(out[1]),
+                "slab_us_per_iter": out[2] * 1e6, "default_us_per_iter": out[3] * 1e6}
+
+    def autotune_load(self, cache_path):
+        return lib().hot_autotune_load(self.h, cache_path.encode()) == HOT_OK
 
     def batch_submit(self, pairs, stream=None, **kw):
         """pairs: list of (mu1, mu2) CUDA tensors.  Returns a Batch handle."""
