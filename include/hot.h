@@ -113,15 +113,16 @@ hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
 
 /* Autotuner of the slab-pass launch shape.  For the shapes and precision of
  * probs (histogram values are ignored: uniform histograms are solved),
- * times `iters` fixed iterations under each candidate workgroup size (2^11 ..
- * 2^17 flow elements per workgroup) and row unroll (1, 2), with hipEvents
+ * times `iters` fixed iterations under each candidate workgroup size (2^13 ..
+ * 2^17 flow elements per workgroup), row unroll (1, 2) and 16-byte vectors
+ * per lane per slab row (2, 4), with hipEvents
  * around every slab pass, and keeps the fastest in ctx for launches of the
  * same total size class and precision.  cache_path (nullable): the choice
  * is appended as a JSON line keyed by device architecture, precision and
  * size class; hot_autotune_load reads such a file (later lines win, entries
- * of other architectures are ignored).  out (nullable, 4 doubles): chosen
- * elements per workgroup, chosen unroll, its slab seconds per iteration, and
- * the built-in rule's.  The chunking changes the summation order of column
+ * of other architectures are ignored).  out (nullable, 5 doubles): chosen
+ * elements per workgroup, chosen unroll, its slab seconds per iteration, the
+ * built-in rule's, chosen vectors per lane.  The chunking changes the summation order of column
  * partial sums, so tuned results can differ from untuned ones by rounding. */
 hot_status hot_autotune(hot_ctx *ctx, const hot_problem *probs, int32_t count,
                         int32_t iters, const char *cache_path, double *out);

@@ -71,13 +71,18 @@ int size_class(int64_t pair_elems) {
 
 int64_t Tuning::item_elems_for(int64_t pair_elems, int fp32) const {  // pair_elems: launch total
   auto it = table.find({fp32, size_class(pair_elems)});
-  if (it != table.end()) return it->second.first;
+  if (it != table.end()) return it->second.item_elems;
   return std::max<int64_t>(2048, std::min<int64_t>(item_elems, pair_elems / std::max<int64_t>(1, min_items)));
 }
 
 int Tuning::unroll_for(int64_t elems, int fp32) const {
   auto it = table.find({fp32, size_class(elems)});
-  return it != table.end() ? it->second.second : unroll;
+  return it != table.end() ? it->second.unroll : unroll;
+}
+
+int Tuning::vec_per_lane_for(int64_t elems, int fp32) const {
+  auto it = table.find({fp32, size_class(elems)});
+  return it != table.end() ? it->second.vec_per_lane : vec_per_lane;
 }
 
 Tuning default_tuning() {
@@ -85,6 +90,9 @@ Tuning default_tuning() {
   t.item_elems = 65536;
   t.min_items = 2048;
   t.unroll = 1;
+  t.vec_per_lane = 4;
+  t.nt_store = 1;
+  t.pingpong = 1;
   return t;
 }
 
@@ -131,7 +139,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       const int Q = F.P / W;
       // about two 16-byte vectors per lane per row: short DPP trees for the
       // row sums, few column accumulators per lane
-      const int LR = std::min(64, next_pow2((Q + 1) / 2));
+      const int vt = tune.vec_per_lane_for(total, fp32);
+      const int LR = std::min(64, next_pow2((Q + vt - 1) / vt));
       const int vpl = (Q + LR - 1) / LR;
       F.lrs = ilog2(LR);
       F.vpl = vpl;
@@ -400,6 +409,7 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     c.max_iter = pr.max_iter;
     c.T = pr.check_every;
     c.flags = (int32_t)pr.flags;
+    if (ctx->tune.pingpong) c.flags |= 0x100;
     c0[np + p] = c;
     c0[np + p].mode = MODE_IDLE;
   }
@@ -636,6 +646,12 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.item_elems = std::max<int64_t>(1024, std::atoll(e));
   e = std::getenv("HOT_MIN_ITEMS");
   if (e) c->tune.min_items = std::max<int64_t>(1, std::atoll(e));
+  e = std::getenv("HOT_VPL_TARGET");
+  if (e) c->tune.vec_per_lane = std::max(1, std::min(8, std::atoi(e)));
+  e = std::getenv("HOT_NT_STORE");
+  if (e) c->tune.nt_store = std::atoi(e) != 0;
+  e = std::getenv("HOT_PINGPONG");
+  if (e) c->tune.pingpong = std::atoi(e) != 0;
   e = std::getenv("HOT_UNROLL");
   if (e) c->tune.unroll = std::atoi(e) >= 2 ? 2 : 1;
   *out = c;
@@ -716,6 +732,7 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
     ws->args.unroll = ctx->tune.unroll_for(total, prec == HOT_FP32_STREAM);
   }
   ws->args.slab_grid = ws->args.nitems;
+  ws->args.nt_store = ctx->tune.nt_store;
   if (s != HOT_OK) return s;
   if (hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking) != hipSuccess) {
     ctx->err = "stream creation failed";

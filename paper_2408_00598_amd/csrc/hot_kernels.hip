@@ -26,11 +26,13 @@ template <>
 struct VecT<float> {
   static constexpr int W = 4;
   typedef float4 type;
+  typedef float native __attribute__((ext_vector_type(4)));
 };
 template <>
 struct VecT<double> {
   static constexpr int W = 2;
   typedef double2 type;
+  typedef double native __attribute__((ext_vector_type(2)));
 };
 
 __device__ inline float vget(const float4& v, int e) {
@@ -113,12 +115,13 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
   typedef typename VecT<T>::type VT;
   const int LR = 1 << x.lrs, rpw = 64 >> x.lrs;
   const int L = x.L, P = x.P;
-  for (int pb = x.r0 + x.wave * rpw; pb < x.r1; pb += 4 * U * rpw) {
-    int prow[U];
-    bool rvv[U];
-    VT xs[U][MAXVPL], xa[U][MAXVPL];
+  constexpr int UR = U & 3;
+  for (int pb = x.r0 + x.wave * rpw; pb < x.r1; pb += 4 * UR * rpw) {
+    int prow[UR];
+    bool rvv[UR];
+    VT xs[UR][MAXVPL], xa[UR][MAXVPL];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UR; ++u) {
       prow[u] = pb + u * 4 * rpw + x.slot;
       rvv[u] = prow[u] < x.r1;
 #pragma unroll
@@ -131,7 +134,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UR; ++u) {
       const int p = prow[u];
       const bool rv = rvv[u];
       const double ap = rv ? alpha[p] : 0.0;
@@ -176,7 +179,12 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
             colacc[v][e] += sd;
             vset(out, e, st);
           }
-          *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
+          if (U & 4)
+            __builtin_nontemporal_store(
+                __builtin_bit_cast(typename VecT<T>::native, out),
+                reinterpret_cast<typename VecT<T>::native*>(dst + (int64_t)p * P + q0));
+          else
+            *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
         }
       }
       rowacc = group_sum(rowacc, LR);
@@ -611,7 +619,8 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
   // evaluates w_bar^K
   nx.mode = fixed ? (nx.it >= c.max_iter ? MODE_CHECK : MODE_NORMAL)
                   : ((nx.k % c.T == 0 || nx.it >= c.max_iter) ? MODE_CHECK : MODE_NORMAL);
-  nx.dst = (nx.mode == MODE_CHECK || nx.src == 2) ? (nx.src == 0 ? 1 : 0) : nx.src;
+  const bool pingpong = (c.flags & 0x100) != 0;  // never update the state in place
+  nx.dst = (pingpong || nx.mode == MODE_CHECK || nx.src == 2) ? (nx.src == 0 ? 1 : 0) : nx.src;
 }
 
 // ---------------------------------------------------------------------------
@@ -1039,16 +1048,22 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 // ---------------------------------------------------------------------------
 
 
+template <typename T, int V, int U>
+static void launch_lean(const LaunchArgs& a, int par, hipStream_t st) {
+  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+                     a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
+                     a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+}
+
 template <typename T, int V>
 static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
-  if (a.unroll >= 2)
-    hipLaunchKernelGGL((k_slab_pass<T, V, 0, 2>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
-                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
-  else
-    hipLaunchKernelGGL((k_slab_pass<T, V, 0, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
-                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+  const int u = (a.unroll >= 2 ? 2 : 1) | (a.nt_store ? 4 : 0);
+  switch (u) {
+    case 1: launch_lean<T, V, 1>(a, par, st); break;
+    case 2: launch_lean<T, V, 2>(a, par, st); break;
+    case 5: launch_lean<T, V, 5>(a, par, st); break;
+    default: launch_lean<T, V, 6>(a, par, st); break;
+  }
   hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
                      a.nitems, a.geo,
                      a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab, a.rowsum[par],

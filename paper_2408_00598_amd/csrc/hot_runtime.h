@@ -21,12 +21,21 @@ struct Tuning {
   int64_t item_elems;   // largest target of elements per slab-pass workgroup
   int64_t min_items;    // aim for at least this many slab-pass workgroups per launch
   int unroll;           // rows loaded ahead per wave (1 or 2)
+  int vec_per_lane;     // target 16-byte vectors per lane per slab row (2 or 4)
+  int nt_store;         // non-temporal stores of the new state
+  int pingpong;         // never update the state in place (read one buffer, write the other)
   // autotuned elements per workgroup, keyed by (precision, log2 of the
   // launch's flow elements); overrides the rule above for that size class
-  std::map<std::pair<int, int>, std::pair<int64_t, int>> table;  // -> (elements, unroll)
+  struct Choice {
+    int64_t item_elems;
+    int unroll;
+    int vec_per_lane;
+  };
+  std::map<std::pair<int, int>, Choice> table;
   // elements per slab-pass workgroup for a launch over `elems` flow elements
   int64_t item_elems_for(int64_t elems, int fp32) const;
   int unroll_for(int64_t elems, int fp32) const;
+  int vec_per_lane_for(int64_t elems, int fp32) const;
 };
 Tuning default_tuning();
 int size_class(int64_t pair_elems);
@@ -51,6 +60,7 @@ struct LaunchArgs {
   int maxvpl = 1;
   int unroll = 1;  // rows loaded ahead per wave in the plain update pass
   int slab_grid = 1;  // workgroups of a slab-pass launch (<= nitems)
+  int nt_store = 0;   // non-temporal stores of the new state
   unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes
 };
 

@@ -65,18 +65,17 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
   const std::pair<int, int> key{prec == HOT_FP32_STREAM, cls};
   const Tuning saved = ctx->tune;
   double best = 1e300, dflt = 0.0;
-  int64_t best_e = 0;
-  int best_u = 1;
+  Tuning::Choice bestc{0, 1, 4};
   hot_status status = HOT_OK;
-  std::vector<std::pair<int64_t, int>> cands;
-  cands.push_back({0, saved.unroll});  // the built-in rule first (reference)
-  for (int64_t e = 2048; e <= 131072; e *= 2)
-    for (int u = 1; u <= 2; ++u) cands.push_back({e, u});
+  std::vector<Tuning::Choice> cands;
+  cands.push_back({0, saved.unroll, saved.vec_per_lane});  // the built-in rule (reference)
+  for (int64_t e = 8192; e <= 131072; e *= 2)
+    for (int u = 1; u <= 2; ++u)
+      for (int v = 2; v <= 4; v += 2) cands.push_back({e, u, v});
   for (size_t c = 0; c < cands.size() && status == HOT_OK; ++c) {
     Tuning t = saved;
     t.table.erase(key);
-    if (cands[c].first > 0) t.table[key] = cands[c];
-    else t.unroll = cands[c].second;
+    if (cands[c].item_elems > 0) t.table[key] = cands[c];
     hot_ctx tmp;
     tmp.device = ctx->device;
     tmp.tune = t;
@@ -96,32 +95,33 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
     if (c == 0) dflt = secs;
     if (c > 0 && secs < best) {
       best = secs;
-      best_e = cands[c].first;
-      best_u = cands[c].second;
+      bestc = cands[c];
     }
   }
   for (void* b : bufs) (void)hipFree(b);
   if (status != HOT_OK) return status;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    ctx->tune.table[key] = {best_e, best_u};
+    ctx->tune.table[key] = bestc;
   }
   if (cache_path && cache_path[0]) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
       std::fprintf(f,
                    "{\"arch\": \"%s\", \"fp32\": %d, \"size_class\": %d, \"item_elems\": %lld, "
-                   "\"unroll\": %d, \"slab_us_per_iter\": %.3f, \"default_us_per_iter\": %.3f}\n",
-                   arch_name(ctx->device).c_str(), key.first, cls, (long long)best_e, best_u,
-                   best * 1e6, dflt * 1e6);
+                   "\"unroll\": %d, \"vec_per_lane\": %d, \"slab_us_per_iter\": %.3f, "
+                   "\"default_us_per_iter\": %.3f}\n",
+                   arch_name(ctx->device).c_str(), key.first, cls, (long long)bestc.item_elems,
+                   bestc.unroll, bestc.vec_per_lane, best * 1e6, dflt * 1e6);
       std::fclose(f);
     }
   }
   if (out) {
-    out[0] = (double)best_e;
-    out[1] = (double)best_u;
+    out[0] = (double)bestc.item_elems;
+    out[1] = (double)bestc.unroll;
     out[2] = best;
     out[3] = dflt;
+    out[4] = (double)bestc.vec_per_lane;
   }
   return HOT_OK;
 }
@@ -135,15 +135,15 @@ extern "C" hot_status hot_autotune_load(hot_ctx* ctx, const char* cache_path) {
   int loaded = 0;
   while (std::fgets(line, sizeof(line), f)) {
     char a[64] = {0};
-    int fp32 = 0, cls = 0, u = 1;
+    int fp32 = 0, cls = 0, u = 1, v = 4;
     long long e = 0;
     if (std::sscanf(line,
                     "{\"arch\": \"%63[^\"]\", \"fp32\": %d, \"size_class\": %d, \"item_elems\": "
-                    "%lld, \"unroll\": %d",
-                    a, &fp32, &cls, &e, &u) == 5 &&
-        arch == a && e >= 1024 && (u == 1 || u == 2)) {
+                    "%lld, \"unroll\": %d, \"vec_per_lane\": %d",
+                    a, &fp32, &cls, &e, &u, &v) == 6 &&
+        arch == a && e >= 1024 && (u == 1 || u == 2) && (v == 2 || v == 4)) {
       std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->tune.table[{fp32, cls}] = {(int64_t)e, u};  // later lines win
+      ctx->tune.table[{fp32, cls}] = Tuning::Choice{(int64_t)e, u, v};  // later lines win
       ++loaded;
     }
   }

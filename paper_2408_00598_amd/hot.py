@@ -210,13 +210,14 @@ class Context:
     def autotune(self, pairs, iters=40, cache_path=None, **kw):
         """Tune the slab-pass launch shape for these shapes / precision."""
         probs = (Problem * len(pairs))(*[self.problem(a, b, **kw) for a, b in pairs])
-        out = (C.c_double * 4)()
+        out = (C.c_double * 5)()
         st = lib().hot_autotune(self.h, probs, len(pairs), iters,
                                 cache_path.encode() if cache_path else None, out)
         if st != HOT_OK:
             raise HotError(st, self.last_error())
         return {"item_elems": int(out[0]), "unroll": int(out[1]),
-                "slab_us_per_iter": out[2] * 1e6, "default_us_per_iter": out[3] * 1e6}
+                "slab_us_per_iter": out[2] * 1e6, "default_us_per_iter": out[3] * 1e6,
+                "vec_per_lane": int(out[4])}
 
     def autotune_load(self, cache_path):
         return lib().hot_autotune_load(self.h, cache_path.encode()) == HOT_OK
