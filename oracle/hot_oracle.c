@@ -218,6 +218,17 @@ void or_kkt(int32_t m, int32_t n, const double *mu1, const double *mu2,
   }
   or_A(m, n, x, r);
   for (int64_t q = 0; q < M3; ++q) r[q] -= b[q];
+  /* R(w) = (b - A x, z - Pi_+(z - x), c - A^T y - z); for z >= 0 the middle
+   * block equals min(x, z) elementwise */
+  double msum = 0.0;
+  for (int64_t e = 0; e < N; ++e) {
+    double pz = z[e] - x[e];
+    pz = pz > 0.0 ? pz : 0.0;
+    double v = z[e] - pz;
+    msum += v * v;
+  }
+  const double rp2 = dot(M3, r, r);
+  res->kkt_abs = sqrt(rp2 + msum + dsum);
   res->res_dual = sqrt(dsum) / (1.0 + nrm2(N, c));
   res->res_comp = sqrt(csum) / (1.0 + nrm2(N, x) + nrm2(N, z));
   res->res_primal = nrm2(M3, r) / (1.0 + nrm2(M3, b));
@@ -296,12 +307,13 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
           acc += v * v;
         }
         r_last = 2.0 * sqrt(acc);
-        if (p->tol > 0 && res->kkt <= p->tol) {
+        const double crit = p->abs_kkt ? res->kkt_abs : res->kkt;
+        if (p->tol > 0 && crit <= p->tol) {
           converged = 1;
           break;
         }
         if (last) break;
-        if (p->restart) {
+        if (p->restart && !(p->admm_rho > 0)) {
           if (k == 0) {
             r_start = r_last;
             r_prev = r_last;
@@ -323,13 +335,24 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
         }
       }
     }
-    /* Step 4: w^{k+1} = w^0/(k+2) + (k+1)/(k+2) (2 w_bar - w) */
-    const double a = 1.0 / (double)(k + 2), bb = (double)(k + 1) / (double)(k + 2);
-    for (int64_t e = 0; e < N; ++e) {
-      x[e] = a * x0[e] + bb * (2.0 * xbar[e] - x[e]);
-      z[e] = a * z0[e] + bb * (2.0 * zbar[e] - z[e]);
+    if (p->admm_rho > 0) {
+      /* generalized ADMM baseline of the experiments (Sec. 4.1): Step 4
+       * replaced by w^{k+1} = (1 - rho) w^k + rho w_bar^k */
+      const double rho = p->admm_rho;
+      for (int64_t e = 0; e < N; ++e) {
+        x[e] = (1.0 - rho) * x[e] + rho * xbar[e];
+        z[e] = (1.0 - rho) * z[e] + rho * zbar[e];
+      }
+      for (int64_t q = 0; q < M3; ++q) y[q] = (1.0 - rho) * y[q] + rho * ybar[q];
+    } else {
+      /* Step 4: w^{k+1} = w^0/(k+2) + (k+1)/(k+2) (2 w_bar - w) */
+      const double a = 1.0 / (double)(k + 2), bb = (double)(k + 1) / (double)(k + 2);
+      for (int64_t e = 0; e < N; ++e) {
+        x[e] = a * x0[e] + bb * (2.0 * xbar[e] - x[e]);
+        z[e] = a * z0[e] + bb * (2.0 * zbar[e] - z[e]);
+      }
+      for (int64_t q = 0; q < M3; ++q) y[q] = a * y0[q] + bb * (2.0 * ybar[q] - y[q]);
     }
-    for (int64_t q = 0; q < M3; ++q) y[q] = a * y0[q] + bb * (2.0 * ybar[q] - y[q]);
     ++k;
     ++it;
   }

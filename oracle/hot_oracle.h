@@ -33,6 +33,8 @@ typedef struct {
   double sigma;      /* > 0: use it; <= 0: sigma = ||b|| / ||c|| */
   int32_t restart;   /* 1: restart rule on, 0: Algorithm 2 verbatim */
   int32_t fixed_iters; /* > 0: run exactly this many updates, no stop test */
+  double admm_rho;   /* > 0: Step 4 replaced by w <- (1-rho) w + rho w_bar (no restarts) */
+  int32_t abs_kkt;   /* 1: stop on the absolute residual ||R(w_bar)|| instead of eq. kkt_res */
 } or_params;
 
 typedef struct {
@@ -44,6 +46,7 @@ typedef struct {
   double res_primal;   /* ||A xbar - b|| / (1 + ||b||) */
   double sigma;
   double fp_res;       /* ||s - shat|| with s = x/sigma + z: fixed-point residual */
+  double kkt_abs;      /* ||R(w_bar)||: the residual map of the complexity proposition */
   int32_t iters;       /* number of updates performed */
   int32_t restarts;
   int32_t converged;

@@ -19,14 +19,15 @@ I32 = C.POINTER(C.c_int32)
 class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("sigma", C.c_double),
-                ("restart", C.c_int32), ("fixed_iters", C.c_int32)]
+                ("restart", C.c_int32), ("fixed_iters", C.c_int32),
+                ("admm_rho", C.c_double), ("abs_kkt", C.c_int32)]
 
 
 class Result(C.Structure):
     _fields_ = [("primal_obj", C.c_double), ("dual_obj", C.c_double),
                 ("kkt", C.c_double), ("res_dual", C.c_double),
                 ("res_comp", C.c_double), ("res_primal", C.c_double),
-                ("sigma", C.c_double), ("fp_res", C.c_double),
+                ("sigma", C.c_double), ("fp_res", C.c_double), ("kkt_abs", C.c_double),
                 ("iters", C.c_int32), ("restarts", C.c_int32),
                 ("converged", C.c_int32)]
 
@@ -127,14 +128,15 @@ def kkt(mu1, mu2, x, y, z):
 
 
 def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
-        restart=True, fixed_iters=0):
+        restart=True, fixed_iters=0, admm_rho=0.0, abs_kkt=False):
     """Run Algorithm 2; returns (xbar, ybar, zbar, s_state, result dict)."""
     mu1, mu2 = _f64(mu1), _f64(mu2)
     m, n = mu1.shape
     N, M3 = dims(m, n)
     xb, zb, s = np.empty(N), np.empty(N), np.empty(N)
     yb = np.empty(M3)
-    p = Params(tol, max_iter, check_every, sigma, 1 if restart else 0, fixed_iters)
+    p = Params(tol, max_iter, check_every, sigma, 1 if restart else 0, fixed_iters, admm_rho,
+               1 if abs_kkt else 0)
     r = Result()
     lib().or_hot(m, n, _d(mu1), _d(mu2), C.byref(p), _d(xb), _d(yb), _d(zb), _d(s),
                  C.byref(r))

@@ -163,3 +163,57 @@ def test_halpern_rate_bound(oracle):
         r3 = c - oracle.AT(m, n, yb) - zb
         nrm = np.sqrt(r1 @ r1 + r2 @ r2 + r3 @ r3)
         assert nrm <= 1.001 * (sigma + 1) / sigma * R0 / (k + 1)
+
+
+@pytest.mark.parametrize("m,n", [(3, 4), (5, 5)])
+def test_generalized_admm_reaches_lp_optimum(oracle, m, n):
+    """The ADMM baseline (Step 4 replaced by the rho = 1.7 relaxation,
+    Sec. 4.1) converges to the same LP optimum."""
+    rng = np.random.default_rng(3 * m + n)
+    mu1, mu2 = rand_hist(rng, m, n), rand_hist(rng, m, n)
+    Ar, br, cr = reduced_lp(mu1, mu2, oracle)
+    st, _, opt = oracle.simplex(Ar, br, cr)
+    _, _, _, _, res = oracle.hot(mu1, mu2, tol=1e-10, max_iter=2000000, admm_rho=1.7)
+    assert st == 0 and res["converged"] == 1 and res["restarts"] == 0
+    assert abs(res["primal_obj"] - opt) <= 1e-6 * abs(opt)
+
+
+def test_absolute_kkt_is_residual_map_norm(oracle):
+    """||R(w_bar)|| of the complexity proposition, recomputed from the
+    exported iterate with numpy, equals the reported absolute KKT, and the
+    absolute stopping rule stops on it."""
+    m, n = 4, 5
+    rng = np.random.default_rng(12)
+    mu1, mu2 = rand_hist(rng, m, n), rand_hist(rng, m, n)
+    c, b = oracle.cost(m, n), oracle.bvec(mu1, mu2)
+    xb, yb, zb, _, res = oracle.hot(mu1, mu2, fixed_iters=37)
+    r1 = b - oracle.A(m, n, xb)
+    r2 = zb - np.maximum(zb - xb, 0.0)
+    r3 = c - oracle.AT(m, n, yb) - zb
+    ref = np.sqrt(r1 @ r1 + r2 @ r2 + r3 @ r3)
+    assert abs(res["kkt_abs"] - ref) <= 1e-12 * ref
+    _, _, _, _, r = oracle.hot(mu1, mu2, tol=1e-5, abs_kkt=True, max_iter=400000)
+    assert r["converged"] == 1 and r["kkt_abs"] <= 1e-5
+
+
+@pytest.mark.parametrize("m,n,seed", [(3, 4, 1), (5, 3, 3)])
+def test_complexity_bound_along_trajectory(oracle, m, n, seed):
+    """Prop. complexity: for Algorithm 2 without restarts and w^0 = 0,
+    ||R(w_bar^k)|| <= ((sigma+1)/sigma) R0/(k+1) with
+    R0 = ||x* + sigma z*|| for a KKT point (x*, y*, z*).  The KKT point comes
+    from HiGHS (primal x*, equality duals y*, z* = c - A^T y*), not from the
+    oracle."""
+    from scipy.optimize import linprog
+    rng = np.random.default_rng(seed)
+    mu1, mu2 = rand_hist(rng, m, n), rand_hist(rng, m, n)
+    A, b, c = reduced_lp(mu1, mu2, oracle)
+    r = linprog(c, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
+    xs, ys = r.x, r.eqlin.marginals
+    zs = c - A.T @ ys
+    assert zs.min() > -1e-9 and abs(c @ xs - b @ ys) < 1e-9
+    sigma = np.linalg.norm(b) / np.linalg.norm(c)
+    R0 = np.linalg.norm(xs + sigma * zs)
+    for K in (1, 2, 5, 17, 60, 250):
+        res = oracle.hot(mu1, mu2, fixed_iters=K, restart=False)[4]
+        assert res["sigma"] == pytest.approx(sigma, rel=1e-14)
+        assert res["kkt_abs"] <= (sigma + 1) / sigma * R0 / (K + 1) * (1 + 1e-9), K
