@@ -58,6 +58,13 @@ typedef enum {
 #define HOT_FLAG_FIXED_ITERS 0x2u /* run exactly max_iter updates of Alg. 2,
                                      no stopping test, no restart; the result
                                      is w_bar at the final iterate */
+#define HOT_FLAG_ADMM 0x4u        /* generalized ADMM baseline of Sec. 4.1:
+                                     Step 4 of Alg. 2 replaced by
+                                     w <- (1 - rho) w + rho w_bar with
+                                     rho = hot_problem.relax; no restarts */
+#define HOT_FLAG_ABS_KKT 0x8u     /* stop when ||R(w_bar)|| <= tol, R the
+                                     residual map stated before Prop.
+                                     complexity, instead of eq. kkt_res */
 
 typedef struct {
   int32_t m, n;            /* grid rows, columns: 1 <= m, n <= 1024 */
@@ -69,6 +76,8 @@ typedef struct {
   double sigma;            /* penalty sigma of Alg. 2; <= 0 selects ||b||/||c|| */
   int32_t prec;            /* hot_precision */
   uint32_t flags;          /* HOT_FLAG_* */
+  double relax;            /* rho of HOT_FLAG_ADMM, in (0, 2); <= 0 selects
+                              1.7 (the experiments' value); ignored otherwise */
 } hot_problem;
 
 typedef struct {
@@ -80,6 +89,8 @@ typedef struct {
   double res_comp;    /* ||min(x_bar, z_bar)|| / (1 + ||x_bar|| + ||z_bar||) */
   double sigma;       /* sigma used */
   double seconds;     /* wall time of the solve on the host clock */
+  double kkt_abs;     /* ||R(w_bar)|| = sqrt(||b - A x_bar||^2 +
+                         ||min(x_bar, z_bar)||^2 + ||c - A^T y_bar - z_bar||^2) */
   int32_t iters;      /* updates performed (Alg. 2 iterations) */
   int32_t restarts;
   int32_t status;     /* hot_status of this problem */

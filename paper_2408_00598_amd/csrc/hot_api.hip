@@ -337,6 +337,10 @@ static hot_status validate_problem(hot_ctx* ctx, const hot_problem* p) {
     ctx->err = "sigma must be finite";
     return HOT_E_INVALID;
   }
+  if ((p->flags & HOT_FLAG_ADMM) && !(p->relax <= 0.0 || p->relax < 2.0)) {
+    ctx->err = "relax must be in (0, 2)";
+    return HOT_E_INVALID;
+  }
   return HOT_OK;
 }
 
@@ -410,6 +414,7 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     c.T = pr.check_every;
     c.flags = (int32_t)pr.flags;
     if (ctx->tune.pingpong) c.flags |= 0x100;
+    c.relax = (pr.flags & HOT_FLAG_ADMM) ? (pr.relax > 0 ? pr.relax : 1.7) : 0.0;
     c0[np + p] = c;
     c0[np + p].mode = MODE_IDLE;
   }
@@ -598,6 +603,7 @@ void Workspace::fill_result(int p, hot_result* r, double seconds) const {
   r->res_comp = c.res_c;
   r->sigma = c.sigma;
   r->seconds = seconds;
+  r->kkt_abs = c.kkt_abs;
   r->iters = c.it;
   r->restarts = c.restarts;
   r->status = (int32_t)status_of(c.status);

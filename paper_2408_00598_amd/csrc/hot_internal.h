@@ -122,6 +122,7 @@ struct PairCtl {
   double sigma, lam, tol;
   double r_start, r_prev;
   double kkt, res_p, res_d, res_c, pobj, dobj, fp_res;
+  double kkt_abs, relax;  // ||R(w_bar)||; rho of the ADMM baseline (0: Halpern)
   int32_t k, it, restarts, status;
   int32_t mode, src, dst, anc;
   int32_t max_iter, T, flags, pad;

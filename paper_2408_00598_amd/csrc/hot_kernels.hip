@@ -542,7 +542,8 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
   nx = c;
   solve = false;
   const bool fixed = (c.flags & 2) != 0;
-  const bool restart_on = (c.flags & 1) != 0 && !fixed;
+  const bool admm = (c.flags & 4) != 0;
+  const bool restart_on = (c.flags & 1) != 0 && !fixed && !admm;
   switch (c.mode) {
     case MODE_INIT:
       nx.k = 0;
@@ -569,6 +570,8 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
       nx.res_c = sqrt(acc[KP_COMP]) / (1.0 + nx2 + nz2);
       nx.res_p = sqrt(acc[KP_PRIM]) / (1.0 + G.norm_b);
       nx.kkt = fmax(nx.res_d, fmax(nx.res_c, nx.res_p));
+      nx.kkt_abs = sqrt(acc[KP_PRIM] + acc[KP_COMP] + acc[KP_DUAL]);
+      const double crit = (c.flags & 8) ? nx.kkt_abs : nx.kkt;
       nx.pobj = acc[KP_CX];
       nx.dobj = acc[KP_BY];
       nx.fp_res = sqrt(acc[KP_FP]);
@@ -580,7 +583,7 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
       }
       if (!isfinite(nx.kkt) || !isfinite(r) || !isfinite(nx.pobj)) {
         nx.status = ST_NUMERIC;
-      } else if (c.tol > 0 && nx.kkt <= c.tol) {
+      } else if (c.tol > 0 && crit <= c.tol) {
         nx.status = ST_CONVERGED;
       } else if (c.it >= c.max_iter) {
         nx.status = ST_MAXITER;
@@ -614,13 +617,17 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
       break;
   }
   if (nx.status != ST_RUNNING) return;
-  nx.lam = 1.0 / (double)(nx.k + 2);
+  // Halpern weight 1/(k+2) toward the epoch's anchor; for the ADMM baseline
+  // s <- (1 - rho) s + rho s_bar = (1 - rho/2) s + (rho/2) shat, i.e. the
+  // anchor is the current state itself with weight 1 - rho/2
+  nx.lam = admm ? 1.0 - 0.5 * c.relax : 1.0 / (double)(nx.k + 2);
   // fixed mode: plain updates, then one check pass at it == K that only
   // evaluates w_bar^K
   nx.mode = fixed ? (nx.it >= c.max_iter ? MODE_CHECK : MODE_NORMAL)
                   : ((nx.k % c.T == 0 || nx.it >= c.max_iter) ? MODE_CHECK : MODE_NORMAL);
   const bool pingpong = (c.flags & 0x100) != 0;  // never update the state in place
   nx.dst = (pingpong || nx.mode == MODE_CHECK || nx.src == 2) ? (nx.src == 0 ? 1 : 0) : nx.src;
+  if (admm) nx.anc = nx.src;
 }
 
 // ---------------------------------------------------------------------------

@@ -239,6 +239,8 @@ hot_status hot_server_submit(hot_server* S, const hot_problem* prob, uint64_t ta
       (prob->prec != HOT_FP64 && prob->prec != HOT_FP32_STREAM))
     return HOT_E_INVALID;
   if (!(prob->flags & HOT_FLAG_FIXED_ITERS) && !(prob->tol > 0)) return HOT_E_INVALID;
+  if ((prob->flags & HOT_FLAG_ADMM) && !(prob->relax <= 0.0 || prob->relax < 2.0))
+    return HOT_E_INVALID;
   if (footprint_of(*prob, S->ctx->tune) > S->budget) return HOT_E_NOMEM;
   Request r;
   r.prob = *prob;

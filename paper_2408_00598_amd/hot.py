@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libhot.so")
 HOT_OK, HOT_E_INVALID, HOT_E_NOMEM, HOT_E_DEVICE, HOT_E_NOT_CONVERGED = 0, 1, 2, 3, 4
 HOT_E_BUSY, HOT_E_CANCELLED, HOT_E_NUMERIC = 5, 6, 7
 HOT_FP64, HOT_FP32_STREAM = 0, 1
-HOT_FLAG_RESTART, HOT_FLAG_FIXED_ITERS = 0x1, 0x2
+HOT_FLAG_RESTART, HOT_FLAG_FIXED_ITERS, HOT_FLAG_ADMM, HOT_FLAG_ABS_KKT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
     "hot_ctx_create", "hot_ctx_destroy", "hot_ctx_last_error", "hot_status_string",
@@ -37,13 +37,15 @@ class ServerConfig(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("mu1", C.c_void_p), ("mu2", C.c_void_p),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
-                ("sigma", C.c_double), ("prec", C.c_int32), ("flags", C.c_uint32)]
+                ("sigma", C.c_double), ("prec", C.c_int32), ("flags", C.c_uint32),
+                ("relax", C.c_double)]
 
 
 class Result(C.Structure):
     _fields_ = [("primal_obj", C.c_double), ("dual_obj", C.c_double), ("kkt", C.c_double),
                 ("res_primal", C.c_double), ("res_dual", C.c_double), ("res_comp", C.c_double),
-                ("sigma", C.c_double), ("seconds", C.c_double), ("iters", C.c_int32),
+                ("sigma", C.c_double), ("seconds", C.c_double), ("kkt_abs", C.c_double),
+                ("iters", C.c_int32),
                 ("restarts", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
@@ -175,13 +177,13 @@ class Context:
         return lib().hot_ctx_last_error(self.h).decode()
 
     def problem(self, mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
-                prec=HOT_FP64, flags=HOT_FLAG_RESTART):
+                prec=HOT_FP64, flags=HOT_FLAG_RESTART, relax=0.0):
         mu1, mu2 = _dev_f64(mu1), _dev_f64(mu2)
         m, n = mu1.shape
         if tuple(mu2.shape) != (m, n):
             raise ValueError("histogram shapes differ")
         return Problem(m, n, mu1.data_ptr(), mu2.data_ptr(), tol, max_iter, check_every, sigma,
-                       prec, flags)
+                       prec, flags, relax)
 
     def solve(self, mu1, mu2, keep=False, stream=None, raise_on_error=True, **kw):
         """Run hot_solve; returns (result dict, Solution or None)."""
