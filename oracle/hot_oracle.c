@@ -37,18 +37,29 @@ void or_dims(int32_t m, int32_t n, int64_t *N, int64_t *M3) {
   *M3 = 3 * (int64_t)m * n - 1;
 }
 
-/* Cost vector c = [c1; c2] (Sec. 2.1 item 3, eq. def:c with p = 2):
- * c1_{i,k,j} = (k-i)^2, c2_{k,j,l} = (j-l)^2. */
-void or_cost(int32_t m, int32_t n, double *c) {
+/* Cost vector c = [c1; c2] (Sec. 2.1 item 3, eq. def:c with p = 2) for a
+ * grid whose row i sits at u_i and column j at v_j:
+ * c1_{i,k,j} = (u_k - u_i)^2, c2_{k,j,l} = (v_j - v_l)^2.  The squared
+ * Euclidean distance between bins (i,j) and (k,l) splits into these two
+ * terms for any such (possibly non-uniform) grid, which is what the
+ * color-transfer application's K-means grid lines use (Sec. 5.3).
+ * u == NULL means u_i = i, v == NULL means v_j = j (the uniform grid). */
+void or_cost_xy(int32_t m, int32_t n, const double *u, const double *v, double *c) {
   for (int32_t j = 0; j < n; ++j)
     for (int32_t k = 0; k < m; ++k)
-      for (int32_t i = 0; i < m; ++i)
-        c[ix1(m, n, i, k, j)] = (double)(k - i) * (double)(k - i);
+      for (int32_t i = 0; i < m; ++i) {
+        const double d = u ? u[k] - u[i] : (double)k - (double)i;
+        c[ix1(m, n, i, k, j)] = d * d;
+      }
   for (int32_t k = 0; k < m; ++k)
     for (int32_t j = 0; j < n; ++j)
-      for (int32_t l = 0; l < n; ++l)
-        c[ix2(m, n, k, j, l)] = (double)(j - l) * (double)(j - l);
+      for (int32_t l = 0; l < n; ++l) {
+        const double d = v ? v[j] - v[l] : (double)j - (double)l;
+        c[ix2(m, n, k, j, l)] = d * d;
+      }
 }
+
+void or_cost(int32_t m, int32_t n, double *c) { or_cost_xy(m, n, NULL, NULL, c); }
 
 /* b = [0_M; mu1; Ibar_M mu2] (eq. Mat:A&b), histograms ordered with the
  * row index fastest, as the Kronecker forms of A3 and A4 imply. */
@@ -200,13 +211,19 @@ static double dot(int64_t len, const double *a, const double *b) {
  * eq. Mat:A&b and the full cost vector c. */
 void or_kkt(int32_t m, int32_t n, const double *mu1, const double *mu2,
             const double *x, const double *y, const double *z, or_result *res) {
+  or_kkt_xy(m, n, NULL, NULL, mu1, mu2, x, y, z, res);
+}
+
+void or_kkt_xy(int32_t m, int32_t n, const double *cu, const double *cv,
+               const double *mu1, const double *mu2, const double *x,
+               const double *y, const double *z, or_result *res) {
   int64_t N, M3;
   or_dims(m, n, &N, &M3);
   double *c = (double *)malloc((size_t)N * sizeof(double));
   double *b = (double *)malloc((size_t)M3 * sizeof(double));
   double *v = (double *)malloc((size_t)N * sizeof(double));
   double *r = (double *)malloc((size_t)M3 * sizeof(double));
-  or_cost(m, n, c);
+  or_cost_xy(m, n, cu, cv, c);
   or_bvec(m, n, mu1, mu2, b);
   or_AT(m, n, y, v);
   double dsum = 0.0, csum = 0.0;
@@ -269,7 +286,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   double *tmp = (double *)malloc((size_t)N * sizeof(double));
   double *aty = (double *)malloc((size_t)N * sizeof(double));
   double *R = (double *)malloc((size_t)M3 * sizeof(double));
-  or_cost(m, n, c);
+  or_cost_xy(m, n, p->coord_row, p->coord_col, c);
   or_bvec(m, n, mu1, mu2, b);
   /* sigma = ||b||/||c||; on a 1 x 1 grid every cost is zero and the ratio is
    * undefined, so sigma = 1 there. */
@@ -300,7 +317,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
     } else {
       int32_t last = (it >= p->max_iter);
       if (k % T == 0 || last) {
-        or_kkt(m, n, mu1, mu2, xbar, ybar, zbar, res);
+        or_kkt_xy(m, n, p->coord_row, p->coord_col, mu1, mu2, xbar, ybar, zbar, res);
         double acc = 0.0;
         for (int64_t e = 0; e < N; ++e) {
           double v = (x[e] - xbar[e]) / sigma + (z[e] - zbar[e]);
@@ -356,7 +373,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
     ++k;
     ++it;
   }
-  if (fixed) or_kkt(m, n, mu1, mu2, xbar, ybar, zbar, res);
+  if (fixed) or_kkt_xy(m, n, p->coord_row, p->coord_col, mu1, mu2, xbar, ybar, zbar, res);
   if (s_state)
     for (int64_t e = 0; e < N; ++e) s_state[e] = x[e] / sigma + z[e];
   res->sigma = sigma;

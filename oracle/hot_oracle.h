@@ -35,6 +35,8 @@ typedef struct {
   int32_t fixed_iters; /* > 0: run exactly this many updates, no stop test */
   double admm_rho;   /* > 0: Step 4 replaced by w <- (1-rho) w + rho w_bar (no restarts) */
   int32_t abs_kkt;   /* 1: stop on the absolute residual ||R(w_bar)|| instead of eq. kkt_res */
+  const double *coord_row; /* m grid-line positions u_i, or NULL for u_i = i */
+  const double *coord_col; /* n grid-line positions v_j, or NULL for v_j = j */
 } or_params;
 
 typedef struct {
@@ -54,12 +56,16 @@ typedef struct {
 
 void or_dims(int32_t m, int32_t n, int64_t *N, int64_t *M3);
 void or_cost(int32_t m, int32_t n, double *c);
+void or_cost_xy(int32_t m, int32_t n, const double *u, const double *v, double *c);
 void or_bvec(int32_t m, int32_t n, const double *mu1, const double *mu2, double *b);
 void or_A(int32_t m, int32_t n, const double *x, double *out);
 void or_AT(int32_t m, int32_t n, const double *y, double *out);
 void or_solve_aat(int32_t m, int32_t n, const double *R, double *y);
 void or_kkt(int32_t m, int32_t n, const double *mu1, const double *mu2,
             const double *x, const double *y, const double *z, or_result *res);
+void or_kkt_xy(int32_t m, int32_t n, const double *cu, const double *cv,
+               const double *mu1, const double *mu2, const double *x,
+               const double *y, const double *z, or_result *res);
 int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
                const or_params *p, double *xbar, double *ybar, double *zbar,
                double *s_state, or_result *res);

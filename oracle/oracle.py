@@ -20,7 +20,8 @@ class Params(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("sigma", C.c_double),
                 ("restart", C.c_int32), ("fixed_iters", C.c_int32),
-                ("admm_rho", C.c_double), ("abs_kkt", C.c_int32)]
+                ("admm_rho", C.c_double), ("abs_kkt", C.c_int32),
+                ("coord_row", D), ("coord_col", D)]
 
 
 class Result(C.Structure):
@@ -42,11 +43,13 @@ def lib():
         L = _lib
         L.or_dims.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.or_cost.argtypes = [C.c_int32, C.c_int32, D]
+        L.or_cost_xy.argtypes = [C.c_int32, C.c_int32, D, D, D]
         L.or_bvec.argtypes = [C.c_int32, C.c_int32, D, D, D]
         L.or_A.argtypes = [C.c_int32, C.c_int32, D, D]
         L.or_AT.argtypes = [C.c_int32, C.c_int32, D, D]
         L.or_solve_aat.argtypes = [C.c_int32, C.c_int32, D, D]
         L.or_kkt.argtypes = [C.c_int32, C.c_int32, D, D, D, D, D, C.POINTER(Result)]
+        L.or_kkt_xy.argtypes = [C.c_int32, C.c_int32, D, D, D, D, D, D, D, C.POINTER(Result)]
         L.or_hot.argtypes = [C.c_int32, C.c_int32, D, D, C.POINTER(Params), D, D, D, D,
                              C.POINTER(Result)]
         L.or_hot.restype = C.c_int32
@@ -80,11 +83,31 @@ def dims(m, n):
     return N.value, M3.value
 
 
-def cost(m, n):
+def cost(m, n, coord_row=None, coord_col=None):
+    """c of the reduced model; coord_row/coord_col: grid-line positions
+    (length m / n), None for the uniform grid 0..m-1 / 0..n-1."""
     N, _ = dims(m, n)
     c = np.empty(N)
-    lib().or_cost(m, n, _d(c))
+    if coord_row is None and coord_col is None:
+        lib().or_cost(m, n, _d(c))
+    else:
+        u, v = _coords(m, n, coord_row, coord_col)
+        lib().or_cost_xy(m, n, _dn(u), _dn(v), _d(c))
     return c
+
+
+def _coords(m, n, coord_row, coord_col):
+    u = None if coord_row is None else _f64(coord_row)
+    v = None if coord_col is None else _f64(coord_col)
+    if u is not None and u.shape != (m,):
+        raise ValueError("coord_row must have length m")
+    if v is not None and v.shape != (n,):
+        raise ValueError("coord_col must have length n")
+    return u, v
+
+
+def _dn(a):
+    return None if a is None else _d(a)
 
 
 def bvec(mu1, mu2):
@@ -119,24 +142,27 @@ def solve_aat(m, n, R):
     return y
 
 
-def kkt(mu1, mu2, x, y, z):
+def kkt(mu1, mu2, x, y, z, coord_row=None, coord_col=None):
     mu1, mu2, x, y, z = map(_f64, (mu1, mu2, x, y, z))
     m, n = mu1.shape
+    u, v = _coords(m, n, coord_row, coord_col)
     r = Result()
-    lib().or_kkt(m, n, _d(mu1), _d(mu2), _d(x), _d(y), _d(z), C.byref(r))
+    lib().or_kkt_xy(m, n, _dn(u), _dn(v), _d(mu1), _d(mu2), _d(x), _d(y), _d(z), C.byref(r))
     return r.as_dict()
 
 
 def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
-        restart=True, fixed_iters=0, admm_rho=0.0, abs_kkt=False):
+        restart=True, fixed_iters=0, admm_rho=0.0, abs_kkt=False, coord_row=None,
+        coord_col=None):
     """Run Algorithm 2; returns (xbar, ybar, zbar, s_state, result dict)."""
     mu1, mu2 = _f64(mu1), _f64(mu2)
     m, n = mu1.shape
     N, M3 = dims(m, n)
     xb, zb, s = np.empty(N), np.empty(N), np.empty(N)
     yb = np.empty(M3)
+    u, v = _coords(m, n, coord_row, coord_col)
     p = Params(tol, max_iter, check_every, sigma, 1 if restart else 0, fixed_iters, admm_rho,
-               1 if abs_kkt else 0)
+               1 if abs_kkt else 0, _dn(u), _dn(v))
     r = Result()
     lib().or_hot(m, n, _d(mu1), _d(mu2), C.byref(p), _d(xb), _d(yb), _d(zb), _d(s),
                  C.byref(r))

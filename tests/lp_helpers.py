@@ -71,3 +71,27 @@ def rand_hist(rng, m, n, zeros=0.0):
         if h.sum() == 0:
             h[0, 0] = 1.0
     return h / h.sum()
+
+
+def full_ot_lp_xy(mu1, mu2, u, v):
+    """Eq. model:OT on a grid whose row i sits at u[i] and column j at v[j]:
+    cost (u_i - u_k)^2 + (v_j - v_l)^2 between bins (i,j) and (k,l)."""
+    m, n = mu1.shape
+    pos = np.array([(u[i], v[j]) for i in range(m) for j in range(n)])
+    diff = pos[:, None, :] - pos[None, :, :]
+    c = (diff ** 2).sum(-1).ravel()
+    Aeq, beq, _ = full_ot_lp(mu1, mu2)
+    return Aeq, beq, c
+
+
+def w2_1d_positions(a, b, x):
+    """1-D W2^2 between masses a and b at sorted positions x: the quantile
+    coupling pairs the overlap of [A_{p-1}, A_p) and [B_{q-1}, B_q)."""
+    A, B = np.concatenate([[0], np.cumsum(a)]), np.concatenate([[0], np.cumsum(b)])
+    tot = 0.0
+    for p in range(len(a)):
+        for q in range(len(b)):
+            ov = min(A[p + 1], B[q + 1]) - max(A[p], B[q])
+            if ov > 0:
+                tot += ov * (x[p] - x[q]) ** 2
+    return tot
