@@ -78,6 +78,16 @@ typedef struct {
   uint32_t flags;          /* HOT_FLAG_* */
   double relax;            /* rho of HOT_FLAG_ADMM, in (0, 2); <= 0 selects
                               1.7 (the experiments' value); ignored otherwise */
+  const double *coord_row; /* device, m finite positions u_i of the grid rows,
+                              or NULL for u_i = i */
+  const double *coord_col; /* device, n finite positions v_j of the grid
+                              columns, or NULL for v_j = j.  Bin (i,j) sits at
+                              (u_i, v_j) and the ground cost is the squared
+                              distance (u_i-u_k)^2 + (v_j-v_l)^2: the
+                              non-uniform bins of the color-transfer
+                              application (Sec. 5.3); A and b are unchanged,
+                              only c (eq. def:c) follows the positions.
+                              Positions need not be sorted or distinct. */
 } hot_problem;
 
 typedef struct {

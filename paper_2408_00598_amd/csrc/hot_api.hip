@@ -122,7 +122,7 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   // never more than item_elems elements each (or the autotuned size for
   // this total)
   const int64_t item_elems = tune.item_elems_for(total, fp32);
-  int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0;
+  int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0, taboff = 0;
   int maxvpl = 1;
   for (size_t p = 0; p < shapes.size(); ++p) {
     const int m = shapes[p].first, n = shapes[p].second;
@@ -158,6 +158,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       aboff += (int64_t)F.nslab * 2 * F.L;
       F.sumoff = aboff;
       aboff += (int64_t)F.nslab * 2;
+      F.xoff = taboff;  // relative to the table region, which follows all pairs
+      taboff += 2 * (int64_t)F.L + 1;
       F.rsoff = rsoff;
       rsoff += (int64_t)F.nslab * F.L;
       F.cpoff = cpoff;
@@ -188,7 +190,11 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
     lay.geo.push_back(g);
   }
   lay.state_elems = round_up(std::max<int64_t>(soff, 64), 64);
-  lay.ab_len = std::max<int64_t>(aboff, 1);
+  for (PairGeo& g : lay.geo)
+    for (int fam = 0; fam < 2; ++fam) g.f[fam].xoff += aboff;
+  lay.tab_off = aboff;
+  lay.tab_len = taboff;
+  lay.ab_len = aboff + taboff;
   lay.rs_len = std::max<int64_t>(rsoff, 1);
   lay.cp_len = std::max<int64_t>(cpoff, 1);
   lay.arr_len = std::max<int64_t>(moff, 1);
@@ -366,6 +372,24 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   HIPCK(hipGetLastError());
   std::vector<double> stats(np * 2 * 8);
   HIPCK(hipMemcpyAsync(stats.data(), stats_d, stats.size() * 8, hipMemcpyDeviceToHost, st));
+  // grid-line positions of problems with non-uniform bins (m + n per pair)
+  std::vector<int64_t> pos_at(np, -1);
+  int64_t npos = 0;
+  for (size_t p = 0; p < np; ++p)
+    if (probs[p].coord_row || probs[p].coord_col) {
+      pos_at[p] = npos;
+      npos += (int64_t)probs[p].m + probs[p].n;
+    }
+  std::vector<double> pos((size_t)std::max<int64_t>(npos, 1));
+  for (size_t p = 0; p < np; ++p) {
+    if (pos_at[p] < 0) continue;
+    if (probs[p].coord_row)
+      HIPCK(hipMemcpyAsync(&pos[pos_at[p]], probs[p].coord_row, (size_t)probs[p].m * 8,
+                           hipMemcpyDeviceToHost, st));
+    if (probs[p].coord_col)
+      HIPCK(hipMemcpyAsync(&pos[pos_at[p] + probs[p].m], probs[p].coord_col,
+                           (size_t)probs[p].n * 8, hipMemcpyDeviceToHost, st));
+  }
   HIPCK(hipStreamSynchronize(st));
   for (size_t p = 0; p < np; ++p) {
     const double* s1 = &stats[(2 * p) * 8];
@@ -387,6 +411,59 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     PairGeo& g = lay.geo[p];
     g.norm_b = std::sqrt(std::max(0.0, s1[3] + s2[3] - s2[4] * s2[4]));
   }
+  // cost tables (positions, row sums of the slab cost, their total) and ||c||
+  tab_host.assign((size_t)std::max<int64_t>(lay.tab_len, 1), 0.0);
+  int coord = 0;
+  for (size_t p = 0; p < np; ++p) {
+    PairGeo& g = lay.geo[p];
+    double sq4[2];
+    for (int fam = 0; fam < 2; ++fam) {
+      const FamGeo& F = g.f[fam];
+      const int L = F.L;
+      const double* given = nullptr;
+      if (pos_at[p] >= 0 && (fam == 0 ? probs[p].coord_row : probs[p].coord_col))
+        given = &pos[pos_at[p] + (fam == 0 ? 0 : g.m)];
+      double* X = &tab_host[F.xoff - lay.tab_off];
+      double* CR = X + L;
+      double cc = 0.0, q4 = 0.0;
+      for (int q = 0; q < L; ++q) X[q] = given ? given[q] : (double)q;
+      for (int a = 0; a < L; ++a) {
+        if (given) {
+          double r = 0.0;
+          for (int q = 0; q < L; ++q) {
+            const double d = X[a] - X[q];
+            r += d * d;
+            q4 += (d * d) * (d * d);
+          }
+          CR[a] = r;
+        } else {
+          CR[a] = cost_rowsum(L, a);  // exact integers
+        }
+        cc += CR[a];
+      }
+      X[2 * L] = cc;
+      sq4[fam] = given ? q4 : slab_cost_sq(L);
+      if (given) {
+        coord = 1;
+        if (!std::isfinite(cc) || !std::isfinite(q4)) {
+          ctx->err = "grid positions must be finite (problem " + std::to_string(p) + ")";
+          return HOT_E_INVALID;
+        }
+      }
+    }
+    g.norm_c = std::sqrt((double)g.n * sq4[0] + (double)g.m * sq4[1]);
+    if (!std::isfinite(g.norm_c)) {
+      ctx->err = "cost norm overflows (problem " + std::to_string(p) + ")";
+      return HOT_E_INVALID;
+    }
+  }
+  if (graph_exec && graph_coord != coord) {  // captured with the other slab kernel
+    (void)hipGraphExecDestroy(graph_exec);
+    (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+  args.coord = coord;
   HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), np * sizeof(PairGeo), hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(items_d, lay.items.data(), lay.items.size() * sizeof(SlabItem),
                        hipMemcpyHostToDevice, st));
@@ -431,6 +508,8 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     HIPCK(hipMemsetAsync(colpart[q], 0, lay.cp_len * 8, st));
   }
   HIPCK(hipMemsetAsync(ab, 0, lay.ab_len * 8, st));
+  HIPCK(hipMemcpyAsync(ab + lay.tab_off, tab_host.data(), (size_t)lay.tab_len * 8,
+                       hipMemcpyHostToDevice, st));
   HIPCK(hipMemsetAsync(kitem, 0, lay.items.size() * kKI * 8, st));
   HIPCK(hipMemsetAsync(bytes_ctr, 0, 8, st));
   return HOT_OK;
@@ -455,6 +534,7 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
       return HOT_E_DEVICE;
     }
     HIPCK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+    graph_coord = args.coord;
   }
   hipEvent_t ev[2];
   HIPCK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -562,6 +642,7 @@ hot_status Workspace::ensure_graph(hot_ctx* ctx, hipStream_t st) {
     return HOT_E_DEVICE;
   }
   HIPCK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+  graph_coord = args.coord;
   return HOT_OK;
 }
 

@@ -62,7 +62,19 @@ struct FamGeo {
   int64_t rsoff;   // double offset of the row sums (L per slab)
   int64_t cpoff;   // double offset of the column partials (nchunk*L per slab)
   int64_t sumoff;  // double offset of (sum alpha, sum beta) per slab (2 per slab)
+  int64_t xoff;    // double offset of the family's cost table in the alpha/beta
+                   // array: X[L] grid-line positions, CR[L] = sum_q (X_p - X_q)^2,
+                   // then CC = sum_p CR[p]
 };
+
+// cost table of a family (written at set-up, read-only afterwards)
+__host__ __device__ inline const double* fam_x(const double* ab, const FamGeo& F) { return ab + F.xoff; }
+__host__ __device__ inline double fam_cr(const double* ab, const FamGeo& F, int p) {
+  return ab[F.xoff + F.L + p];
+}
+__host__ __device__ inline double fam_cc(const double* ab, const FamGeo& F) {
+  return ab[F.xoff + 2 * (int64_t)F.L];
+}
 
 struct PairGeo {
   int32_t m, n;

@@ -105,10 +105,11 @@ struct SlabCtx {
   double lam, oml, sigma;
 };
 
-template <typename T, int MAXVPL, int MODE, int ANC, int U>
+template <typename T, int MAXVPL, int MODE, int ANC, int U, int C>
 __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
                                  T* __restrict__ dst, const T* __restrict__ anc,
                                  const double* __restrict__ alpha, const double* __restrict__ bl,
+                                 const double* __restrict__ lx,
                                  double (&colacc)[MAXVPL][VecT<T>::W], double* __restrict__ rowsum,
                                  double (&kk)[6]) {
   constexpr int W = VecT<T>::W;
@@ -138,6 +139,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
       const int p = prow[u];
       const bool rv = rvv[u];
       const double ap = rv ? alpha[p] : 0.0;
+      const double xp = (C && rv) ? lx[p] : 0.0;  // row position (non-uniform bins)
       double rowacc = 0.0;
 #pragma unroll
       for (int v = 0; v < MAXVPL; ++v) {
@@ -149,7 +151,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
           for (int e = 0; e < W; ++e) {
             const bool ok = (q0 + e) < L;
             const double s = (double)vget(xs[u][v], e);
-            const double d = d0 - (double)e;
+            const double d = C ? xp - lx[q0 + e] : d0 - (double)e;
             const double g = d * d - (ap + bl[q0 + e]);
             double o;
             if (MODE == MODE_RESTART) {
@@ -196,13 +198,14 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
 // HEAVY = 0: plain update passes; HEAVY = 1: check and restart passes.  Both
 // kernels are launched every iteration; a workgroup whose pair is in the
 // other kind of pass exits at once.
-template <typename T, int MAXVPL, int HEAVY, int U>
+template <typename T, int MAXVPL, int HEAVY, int U, int C>
 __device__ inline void slab_item(
     int item, const SlabItem* __restrict__ items, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
     T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
     double* __restrict__ colpart, double* __restrict__ kitem,
-    unsigned long long* __restrict__ bytes_ctr, double* lds_col, double* lds_beta, double* red) {
+    unsigned long long* __restrict__ bytes_ctr, double* lds_col, double* lds_beta, double* lds_x,
+    double* red) {
   constexpr int W = VecT<T>::W;
   constexpr int S = 64 * MAXVPL * W;
   const SlabItem itm = items[item];
@@ -243,6 +246,10 @@ __device__ inline void slab_item(
   // previous item's readers of lds_col / lds_beta behind us
   __syncthreads();
   for (int q = threadIdx.x; q < F.P; q += kWG) lds_beta[q] = q < L ? beta[q] : 0.0;
+  if (C) {
+    const double* X = fam_x(ab, F);
+    for (int q = threadIdx.x; q < F.P; q += kWG) lds_x[q] = q < L ? X[q] : 0.0;
+  }
   __syncthreads();
 
   double colacc[MAXVPL][W];
@@ -253,20 +260,20 @@ __device__ inline void slab_item(
   double kk[6] = {0, 0, 0, 0, 0, 0};
   if (!HEAVY) {
     if (anc_kind == ANC_ZERO)
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_ZERO, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
     else if (anc_kind == ANC_SAME)
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SAME, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SAME, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
     else
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SEP, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SEP, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
   } else if (mode == MODE_CHECK) {
     if (anc_kind == ANC_ZERO)
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_ZERO, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+      slab_rows<T, MAXVPL, MODE_CHECK, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
     else if (anc_kind == ANC_SAME)
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SAME, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SAME, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
     else
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SEP, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SEP, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
   } else {
-    slab_rows<T, MAXVPL, MODE_RESTART, ANC_ZERO, U>(x, src, dst, anc, alpha, lds_beta, colacc, rs, kk);
+    slab_rows<T, MAXVPL, MODE_RESTART, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
   }
 
   // column partials: fold the row slots of the wave, then the four waves
@@ -308,7 +315,7 @@ __device__ inline void slab_item(
 }
 
 // One workgroup per item.
-template <typename T, int MAXVPL, int HEAVY, int U>
+template <typename T, int MAXVPL, int HEAVY, int U, int C>
 __global__ __launch_bounds__(kWG) void k_slab_pass(
     const SlabItem* __restrict__ items, int nitems, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
@@ -319,10 +326,11 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
   constexpr int S = 64 * MAXVPL * W;
   __shared__ double lds_col[4 * S];
   __shared__ double lds_beta[S];
+  __shared__ double lds_x[C ? S : 1];
   __shared__ double red[4];
   if ((int)blockIdx.x < nitems)
-    slab_item<T, MAXVPL, HEAVY, U>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, ab, rowsum,
-                                   colpart, kitem, bytes_ctr, lds_col, lds_beta, red);
+    slab_item<T, MAXVPL, HEAVY, U, C>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, ab, rowsum,
+                                      colpart, kitem, bytes_ctr, lds_col, lds_beta, lds_x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -335,17 +343,13 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
 //   kind 2, strip s: u2[j] = sum_k rs2[k][j] for 64 columns j.
 // Every access is along a row.  R1 itself is never stored: the solve reads
 // it straight from the two row-sum arrays, tile by tile.
-// With C_L(p) = sum_q (p-q)^2 and CC_L = sum_p C_L(p):
+// With C_L(p) = sum_q (X_p - X_q)^2 and CC_L = sum_p C_L(p) from the family's
+// cost table (X_p = p on the uniform grid):
 //   R1[j][k] = -(rs1[j][k] - C_m(k)) + (rs2[k][j] - C_n(j)),
 //   1^T R1^j = -(tot1[j] - CC_m) + (u2[j] - m C_n(j)),
 //   sum_j R1[j][k] = -(u1[k] - n C_m(k)) + (tot2[k] - CC_n).
 // ---------------------------------------------------------------------------
 __device__ inline double dinv(int m, int k) { return (k == m - 1) ? 1.0 / (m + 1.0) : 1.0 / m; }
-// sum_{j,l < n} (j - l)^2
-__device__ inline double cost_total(int n) {
-  const double dn = (double)n;
-  return dn * dn * (dn * dn - 1.0) / 6.0;
-}
 
 __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const PBlock* __restrict__ blocks, const PairGeo* __restrict__ geo,
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       double pu = 0.0;
       if (col < ncol) {
         vec[(s1 ? vec_u1(G) : vec_u2(G)) + col] = tot;
-        if (s1) pu = (-(tot - (double)n * cost_rowsum(m, col))) * dinv(m, col);
+        if (s1) pu = (-(tot - (double)n * fam_cr(ab, F1, col))) * dinv(m, col);
       }
       if (s1) {
         pu = wave_sum(pu);
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     for (int i = lane; i < m; i += 64) {
       double cs = 0.0;
       for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m + i];
-      const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - cost_rowsum(m, i));
+      const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - fam_cr(ab, F1, i));
       R2[(int64_t)j * m + i] = r2;
       sr2 += r2;
       t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       if (!(k == m - 1 && l == n - 1)) {
         double cs = 0.0;
         for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n + l];
-        r3 = mu2[(int64_t)k * n + l] * isg - (cs - cost_rowsum(n, l));
+        r3 = mu2[(int64_t)k * n + l] * isg - (cs - fam_cr(ab, F2, l));
       }
       R3T[(int64_t)k * n + l] = r3;
       s3 += r3;
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       vec[vec_tot2(G) + k] = t2;
     }
     p_sp = s3;
-    p_u = ((t2 - cost_total(n)) + s3) * dinv(m, k);
+    p_u = ((t2 - fam_cc(ab, F2)) + s3) * dinv(m, k);
   }
   if (lane == 0) {
     wred[wave][0] = p_sa;
@@ -477,9 +481,9 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       const double* al2 = ab + F2.aboff + (int64_t)kk * 2 * n;
       const double sb2 = ab[F2.sumoff + 2 * (int64_t)kk + 1];
       const double x1 = sg * (rowsum_prev[F1.rsoff + (int64_t)j * m + kk] -
-                              (cost_rowsum(m, kk) - m * al[kk] - sb));
+                              (fam_cr(ab, F1, kk) - m * al[kk] - sb));
       const double x2 = sg * (rowsum_prev[F2.rsoff + (int64_t)kk * n + j] -
-                              (cost_rowsum(n, j) - n * al2[j] - sb2));
+                              (fam_cr(ab, F2, j) - n * al2[j] - sb2));
       const double r = x1 - x2;
       prim += r * r;
     }
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     for (int i = lane; i < m; i += 64) {
       double cs = 0.0;
       for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m + i];
-      const double x = sg * (cs - (cost_rowsum(m, i) - sa - m * be[i]));
+      const double x = sg * (cs - (fam_cr(ab, F1, i) - sa - m * be[i]));
       const double r = x - mu1T[(int64_t)j * m + i];
       prim += r * r;
       by += mu1T[(int64_t)j * m + i] * be[i];
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       if (k == m - 1 && l == n - 1) continue;
       double cs = 0.0;
       for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n + l];
-      const double x = sg * (cs - (cost_rowsum(n, l) - sa - n * be[l]));
+      const double x = sg * (cs - (fam_cr(ab, F2, l) - sa - n * be[l]));
       const double r = x - mu2[(int64_t)k * n + l];
       prim += r * r;
       by += mu2[(int64_t)k * n + l] * be[l];
@@ -653,21 +657,22 @@ struct SolveScalars {
 };
 
 template <int FROM_R>
-__device__ inline double b1_of(const PairGeo& G, const double* vec, int j) {
+__device__ inline double b1_of(const PairGeo& G, const double* vec, const double* ab, int j) {
   if (FROM_R) return vec[vec_b1(G) + j];
-  return -(vec[vec_tot1(G) + j] - cost_total(G.m)) +
-         (vec[vec_u2(G) + j] - (double)G.m * cost_rowsum(G.n, j));
+  return -(vec[vec_tot1(G) + j] - fam_cc(ab, G.f[0])) +
+         (vec[vec_u2(G) + j] - (double)G.m * fam_cr(ab, G.f[1], j));
 }
 
 template <int FROM_R>
-__device__ inline double Sp_of(const PairGeo& G, const double* vec, int k) {
+__device__ inline double Sp_of(const PairGeo& G, const double* vec, const double* ab, int k) {
   if (FROM_R) return vec[vec_Sp(G) + k];
-  return -(vec[vec_u1(G) + k] - (double)G.n * cost_rowsum(G.m, k)) +
-         (vec[vec_tot2(G) + k] - cost_total(G.n)) + vec[vec_PR3(G) + k];
+  return -(vec[vec_u1(G) + k] - (double)G.n * fam_cr(ab, G.f[0], k)) +
+         (vec[vec_tot2(G) + k] - fam_cc(ab, G.f[1])) + vec[vec_PR3(G) + k];
 }
 
 template <int FROM_R>
-__device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec, int lane) {
+__device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec, const double* ab,
+                                             int lane) {
   const int m = G.m, n = G.n;
   const double dm = (double)m, dn = (double)n;
   const double* sp_ = vec + vec_spart(G);
@@ -685,7 +690,7 @@ __device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec
   S.sa = sa;
   S.sp = sp;
   S.u = up - (sa / dm) * sdinv;  // 1^T D^{-1} S
-  const double Sl = Sp_of<FROM_R>(G, vec, m - 1) - sa / dm;
+  const double Sl = Sp_of<FROM_R>(G, vec, ab, m - 1) - sa / dm;
   S.tlast = Sl / (dm + 1.0) + dm * (dm + 1.0) * S.u / (dm + 1.0);
   const double tsum = S.u * (1.0 + dm * (dm + 1.0) * sdinv);
   S.sq = tsum - S.tlast / dn;  // 1^T Q t
@@ -693,17 +698,19 @@ __device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec
 }
 
 template <int FROM_R>
-__device__ inline double t_entry(const PairGeo& G, const double* vec, const SolveScalars& S,
+__device__ inline double t_entry(const PairGeo& G, const double* vec, const double* ab,
+                                 const SolveScalars& S,
                                  int k) {
   const double dm = (double)G.m;
   const double d = dinv(G.m, k);
-  return (Sp_of<FROM_R>(G, vec, k) - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
+  return (Sp_of<FROM_R>(G, vec, ab, k) - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
 }
 
 // 1^T (Rhat1^j + Q t)
 template <int FROM_R>
-__device__ inline double rs_of(const PairGeo& G, const double* vec, const SolveScalars& S, int j) {
-  return b1_of<FROM_R>(G, vec, j) - vec[vec_a(G) + j] + S.sp / (double)G.n + S.sq;
+__device__ inline double rs_of(const PairGeo& G, const double* vec, const double* ab,
+                               const SolveScalars& S, int j) {
+  return b1_of<FROM_R>(G, vec, ab, j) - vec[vec_a(G) + j] + S.sp / (double)G.n + S.sq;
 }
 
 // beta of one slab, and the slab's (sum alpha, sum beta): sum_k y1[j][k] =
@@ -718,7 +725,7 @@ __device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const 
     const double* R2 = arr + arr_R2(G);
     const FamGeo F = G.f[0];
     double* be = ab + F.aboff + (int64_t)j * 2 * m + m;
-    const double rsj = rs_of<FROM_R>(G, vec, S, j);
+    const double rsj = rs_of<FROM_R>(G, vec, ab, S, j);
     double sb = 0.0;
     for (int i = lane; i < m; i += 64) {
       const double v = (R2[(int64_t)j * m + i] - rsj / dn) / dm;
@@ -735,7 +742,7 @@ __device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const 
     const double* R3T = arr + arr_R3T(G);
     const FamGeo F = G.f[1];
     double* be = ab + F.aboff + (int64_t)k * 2 * n + n;
-    const double tk = t_entry<FROM_R>(G, vec, S, k);
+    const double tk = t_entry<FROM_R>(G, vec, ab, S, k);
     double sb = 0.0;
     for (int l = lane; l < n; l += 64) {
       const double v = (k == m - 1 && l == n - 1) ? 0.0 : (R3T[(int64_t)k * n + l] + tk) / dn;
@@ -767,17 +774,17 @@ __device__ void solve_alpha_tile(const PairGeo& G, int tile, const double* rowsu
   if (t < 32) {
     const int j = j0 + t;
     if (j < n) {
-      s_rs[t] = rs_of<FROM_R>(G, vec, S, j);
+      s_rs[t] = rs_of<FROM_R>(G, vec, ab, S, j);
       s_a[t] = vec[vec_a(G) + j];
-      s_cn[t] = cost_rowsum(n, j);
+      s_cn[t] = fam_cr(ab, F2, j);
     }
   } else if (t < 64) {
     const int kk = t - 32, k = k0 + kk;
     if (k < m) {
-      const double tk = t_entry<FROM_R>(G, vec, S, k);
+      const double tk = t_entry<FROM_R>(G, vec, ab, S, k);
       s_qt[kk] = (k == m - 1) ? tk - tk / dn : tk;
       s_p3[kk] = vec[vec_PR3(G) + k];
-      s_cm[kk] = cost_rowsum(m, k);
+      s_cm[kk] = fam_cr(ab, F1, k);
     }
   }
   const double* rs1 = rowsum + F1.rsoff;  // [n][m]
@@ -845,7 +852,7 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
       decide(G, c, acc, nx, solve);
     }
     SolveScalars S;
-    if (solve) S = solve_scalars<FROM_R>(G, vec, threadIdx.x);
+    if (solve) S = solve_scalars<FROM_R>(G, vec, ab, threadIdx.x);
     if (threadIdx.x == 0) {
       if (!FROM_R) s_nx = nx;
       s_solve = solve ? 1 : 0;
@@ -943,7 +950,8 @@ __global__ void k_export(const PairGeo* __restrict__ geo, const PairCtl* __restr
     const FamGeo F = G.f[fam];
     const double sv = (double)s[F.soff + ((int64_t)slab * L + p) * F.P + q];
     const double* al = ab + F.aboff + (int64_t)slab * 2 * L;
-    const double d = (double)(p - q);
+    const double* X = fam_x(ab, F);
+    const double d = X[p] - X[q];
     const double g = d * d - al[p] - al[L + q];
     if (xbar) xbar[e] = c.sigma * (sv - g);
     if (zbar) zbar[e] = fmax(0.0, 2.0 * g - sv);
@@ -1055,23 +1063,31 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 // ---------------------------------------------------------------------------
 
 
-template <typename T, int V, int U>
+template <typename T, int V, int U, int C>
 static void launch_lean(const LaunchArgs& a, int par, hipStream_t st) {
-  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U, C>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
                      a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
                      a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
 }
 
 template <typename T, int V>
 static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
+  if (a.coord) {  // non-uniform bins: positions from LDS, one row per wave step
+    if (a.nt_store) launch_lean<T, V, 5, 1>(a, par, st);
+    else launch_lean<T, V, 1, 1>(a, par, st);
+    hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
+                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+    return;
+  }
   const int u = (a.unroll >= 2 ? 2 : 1) | (a.nt_store ? 4 : 0);
   switch (u) {
-    case 1: launch_lean<T, V, 1>(a, par, st); break;
-    case 2: launch_lean<T, V, 2>(a, par, st); break;
-    case 5: launch_lean<T, V, 5>(a, par, st); break;
-    default: launch_lean<T, V, 6>(a, par, st); break;
+    case 1: launch_lean<T, V, 1, 0>(a, par, st); break;
+    case 2: launch_lean<T, V, 2, 0>(a, par, st); break;
+    case 5: launch_lean<T, V, 5, 0>(a, par, st); break;
+    default: launch_lean<T, V, 6, 0>(a, par, st); break;
   }
-  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
+  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, 0>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
                      a.nitems, a.geo,
                      a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab, a.rowsum[par],
                      a.colpart[par], a.kitem, a.bytes_ctr);

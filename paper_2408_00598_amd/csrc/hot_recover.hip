@@ -61,7 +61,8 @@ __global__ void k_clip_flows(const PairGeo* __restrict__ geo, const PairCtl* __r
     const int slab = (int)(t / L);
     const double sv = (double)s[F.soff + ((int64_t)slab * L + p) * F.P + q];
     const double* al = ab + F.aboff + (int64_t)slab * 2 * L;
-    const double d = (double)(p - q);
+    const double* X = fam_x(ab, F);
+    const double d = X[p] - X[q];
     const double g = d * d - al[p] - al[L + q];
     const double x = c.sigma * (sv - g);
     w[e] = x > 0.0 ? x : 0.0;

@@ -61,6 +61,7 @@ struct LaunchArgs {
   int unroll = 1;  // rows loaded ahead per wave in the plain update pass
   int slab_grid = 1;  // workgroups of a slab-pass launch (<= nitems)
   int nt_store = 0;   // non-temporal stores of the new state
+  int coord = 0;      // some pair has non-uniform bins: slab passes read positions
   unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes
 };
 
@@ -72,6 +73,7 @@ struct Layout {
   std::vector<PBlock> blocks;
   std::vector<PBlock> sblocks;
   int64_t state_elems = 0, ab_len = 0, rs_len = 0, cp_len = 0, arr_len = 0, vec_len = 0;
+  int64_t tab_off = 0, tab_len = 0;  // cost tables of every family, inside ab
   int maxvpl = 1;
   size_t bytes() const;
 };
@@ -104,6 +106,8 @@ struct Workspace {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long* bytes_ctr = nullptr;
+  std::vector<double> tab_host;  // cost tables uploaded by setup
+  int graph_coord = 0;           // slab kernel variant the graph was captured with
   // profiling (events around every slab pass; direct launches)
   bool profile = false;
   double prof_seconds = 0.0;

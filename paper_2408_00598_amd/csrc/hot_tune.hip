@@ -60,6 +60,9 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
     p.max_iter = iters;
     p.check_every = 1 << 30;
     p.flags = HOT_FLAG_FIXED_ITERS;
+    p.relax = 0.0;
+    p.coord_row = nullptr;  // the uniform grid (the launch shape does not
+    p.coord_col = nullptr;  // depend on the positions)
   }
   const int cls = size_class(total);
   const std::pair<int, int> key{prec == HOT_FP32_STREAM, cls};

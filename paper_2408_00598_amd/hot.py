@@ -38,7 +38,7 @@ class Problem(C.Structure):
     _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("mu1", C.c_void_p), ("mu2", C.c_void_p),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("sigma", C.c_double), ("prec", C.c_int32), ("flags", C.c_uint32),
-                ("relax", C.c_double)]
+                ("relax", C.c_double), ("coord_row", C.c_void_p), ("coord_col", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -177,13 +177,25 @@ class Context:
         return lib().hot_ctx_last_error(self.h).decode()
 
     def problem(self, mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
-                prec=HOT_FP64, flags=HOT_FLAG_RESTART, relax=0.0):
+                prec=HOT_FP64, flags=HOT_FLAG_RESTART, relax=0.0, coord_row=None,
+                coord_col=None):
+        """Build a hot_problem.  The tensors it points to must stay alive
+        while the problem is in use (callers keep a reference)."""
         mu1, mu2 = _dev_f64(mu1), _dev_f64(mu2)
         m, n = mu1.shape
         if tuple(mu2.shape) != (m, n):
             raise ValueError("histogram shapes differ")
-        return Problem(m, n, mu1.data_ptr(), mu2.data_ptr(), tol, max_iter, check_every, sigma,
-                       prec, flags, relax)
+        cu = None if coord_row is None else _dev_f64(coord_row).reshape(-1)
+        cv = None if coord_col is None else _dev_f64(coord_col).reshape(-1)
+        if cu is not None and cu.numel() != m:
+            raise ValueError("coord_row must have m entries")
+        if cv is not None and cv.numel() != n:
+            raise ValueError("coord_col must have n entries")
+        prob = Problem(m, n, mu1.data_ptr(), mu2.data_ptr(), tol, max_iter, check_every, sigma,
+                       prec, flags, relax, None if cu is None else cu.data_ptr(),
+                       None if cv is None else cv.data_ptr())
+        prob._keep = (mu1, mu2, cu, cv)
+        return prob
 
     def solve(self, mu1, mu2, keep=False, stream=None, raise_on_error=True, **kw):
         """Run hot_solve; returns (result dict, Solution or None)."""
@@ -224,14 +236,25 @@ class Context:
     def autotune_load(self, cache_path):
         return lib().hot_autotune_load(self.h, cache_path.encode()) == HOT_OK
 
+    def _problems(self, pairs, kw):
+        """pairs: (mu1, mu2) or (mu1, mu2, per-pair keyword dict)."""
+        out = []
+        for pr in pairs:
+            extra = pr[2] if len(pr) > 2 else {}
+            out.append(self.problem(pr[0], pr[1], **{**kw, **extra}))
+        return out
+
     def batch_submit(self, pairs, stream=None, **kw):
-        """pairs: list of (mu1, mu2) CUDA tensors.  Returns a Batch handle."""
-        probs = (Problem * len(pairs))(*[self.problem(a, b, **kw) for a, b in pairs])
+        """pairs: list of (mu1, mu2) CUDA tensors, optionally with a third
+        element holding per-pair keywords (e.g. coord_row / coord_col).
+        Returns a Batch handle."""
+        plist = self._problems(pairs, kw)
+        probs = (Problem * len(pairs))(*plist)
         h = C.c_void_p()
         st = lib().hot_batch_submit(self.h, probs, len(pairs), _stream_ptr(stream), C.byref(h))
         if st != HOT_OK:
             raise HotError(st, self.last_error())
-        return Batch(self, h, len(pairs), pairs, probs)
+        return Batch(self, h, len(pairs), (pairs, [p._keep for p in plist]), probs)
 
     def batch_solve(self, pairs, **kw):
         return self.batch_submit(pairs, **kw).wait()

@@ -151,3 +151,16 @@ def serving_pair(n: int, seed: int):
     rng = np.random.default_rng(seed)
     return (gaussian_blobs(n, n, int(rng.integers(1, 6)), rng),
             gaussian_blobs(n, n, int(rng.integers(1, 6)), rng))
+
+
+def grid_lines(L: int, rng, spread: float = 0.7) -> np.ndarray:
+    """Sorted, unevenly spaced positions of L grid lines spanning [0, L-1],
+    as when lines are drawn through clustered K-means centroids (the
+    non-uniform bins of the color-transfer application, Sec. 5.3): gaps are
+    Gamma(spread)-distributed, so some lines bunch up and others are far
+    apart."""
+    if L == 1:
+        return np.zeros(1)
+    gaps = rng.gamma(spread, 1.0, L - 1) + 1e-3
+    x = np.concatenate([[0.0], np.cumsum(gaps)])
+    return x * ((L - 1) / x[-1])
