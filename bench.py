@@ -34,6 +34,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "OT solves/sec to 1e-4 KKT (FP32 batched vs FP64 plain); HBM GB/s; p99 lat"
 PEAK_HBM_GBS = 8000.0
+TUNE_CACHE = os.path.join(ROOT, "paper_2408_00598_amd", "tuned", "gfx950.jsonl")
+
+
+def cached_choice(path, fp32, total, npairs):
+    """Last autotuner cache line for this precision, size class and pair-count
+    class (the library keys its table by floor(log2) of the flow elements and
+    of the pair count)."""
+    if not path or not os.path.exists(path):
+        return None
+    cls, pcls = int(total).bit_length() - 1, int(npairs).bit_length() - 1
+    found = None
+    for line in open(path):
+        try:
+            e = json.loads(line)
+        except ValueError:
+            continue
+        if (e.get("fp32"), e.get("size_class"), e.get("pairs_class")) == (fp32, cls, pcls):
+            found = e
+    return found
+
+
+def launch_key(tuned):
+    if not tuned:
+        return "builtin"
+    return "item_elems={},unroll={},vec_per_lane={}".format(
+        tuned["item_elems"], tuned["unroll"], tuned["vec_per_lane"])
 
 
 def make_workload(name, pairs):
@@ -137,15 +163,17 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, launch):
     """HBM traffic per slab-pass launch from the committed rocprofv3 counter
-    summary of this workload, if it was taken on the current kernel source."""
+    summary of this workload, if it was taken on the current kernel source
+    and launch shape."""
     import hashlib
-    name = {"batched": "slab_pass_batched256_fp32_traffic.md"}.get(workload)
+    name = {"batched": "slab_pass_batched256_fp32_traffic.md",
+            "pair512": "slab_pass_pair512_fp32_traffic.md"}.get(workload)
     if not name:
         return None
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2408_00598_amd", "csrc", "hot_kernels.hip")
+    src = os.path.join(ROOT, "paper_2408_00598_amd", "csrc", "hot_slab.hip")
     if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -154,7 +182,7 @@ def measured_traffic(workload):
         if ":" in line and not line.startswith(("#", "|", "`")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != sha:
+    if vals.get("kernel_source_sha256") != sha or vals.get("launch_config") != launch:
         return None
     try:
         return float(vals["traffic_bytes_per_launch"]) / 1e9
@@ -198,7 +226,12 @@ def main():
     ap.add_argument("--pairs", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="skip tuning the slab-pass launch shape before the warmup")
+                    help="use the built-in launch-shape rule (no cache, no tuning)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="JSON-lines autotuner cache; a matching entry is loaded instead of "
+                         "tuning live")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune live before the warmup and append the choice to --tune-cache")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--plan", action="store_true", help="recover plans inside each step")
     ap.add_argument("--duration", type=float, default=10.0, help="serving trace length (s)")
@@ -241,7 +274,17 @@ def main():
 
     tuned = None
     if not args.no_autotune:
-        tuned = ctx.autotune(dpairs, iters=30, prec=prec)
+        fp32 = int(prec == hot.HOT_FP32_STREAM)
+        total = sum(a.shape[0] ** 2 * a.shape[1] + a.shape[0] * a.shape[1] ** 2 for a, _ in pairs)
+        hit = None if args.retune else cached_choice(args.tune_cache, fp32, total, len(pairs))
+        if hit is not None and ctx.autotune_load(args.tune_cache):
+            tuned = {k: hit[k] for k in ("item_elems", "unroll", "vec_per_lane",
+                                         "slab_us_per_iter", "default_us_per_iter")}
+            tuned["source"] = "cache"
+        else:
+            tuned = ctx.autotune(dpairs, iters=30, prec=prec,
+                                 cache_path=args.tune_cache if args.retune else None)
+            tuned["source"] = "live"
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -259,7 +302,7 @@ def main():
     prof = ctx.profile()
     ctx.set_profiling(False)
     achieved = prof["slab_bytes"] / prof["slab_seconds"] / 1e9 if prof["slab_seconds"] else 0.0
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(args.workload, launch_key(tuned))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS,
                 "traffic": traffic,  # GB per launch (rocprofv3 FETCH/WRITE, copy-calibrated)
@@ -277,6 +320,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "pairs": len(dpairs), "tol": tol},
         "autotune": tuned,
+        "launch_config": launch_key(tuned),
         "roofline": roofline,
         "solve_stats": {"iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
                         "kkt_max": float(max(r["kkt"] for r in results)),

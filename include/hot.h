@@ -138,10 +138,12 @@ hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
  * 2^17 flow elements per workgroup), row unroll (1, 2) and 16-byte vectors
  * per lane per slab row (2, 4), with hipEvents
  * around every slab pass, and keeps the fastest in ctx for launches of the
- * same total size class and precision.  cache_path (nullable): the choice
- * is appended as a JSON line keyed by device architecture, precision and
- * size class; hot_autotune_load reads such a file (later lines win, entries
- * of other architectures are ignored).  out (nullable, 5 doubles): chosen
+ * same precision, size class (floor(log2) of the total flow elements) and
+ * pair-count class (floor(log2) of the number of problems).  cache_path
+ * (nullable): the choice is appended as a JSON line keyed by device
+ * architecture, precision, size class and pair-count class;
+ * hot_autotune_load reads such a file (later lines win, entries of other
+ * architectures are ignored).  out (nullable, 5 doubles): chosen
  * elements per workgroup, chosen unroll, its slab seconds per iteration, the
  * built-in rule's, chosen vectors per lane.  The chunking changes the summation order of column
  * partial sums, so tuned results can differ from untuned ones by rounding. */

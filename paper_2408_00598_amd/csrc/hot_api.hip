@@ -63,25 +63,25 @@ static double slab_cost_sq(int L) {
   return (double)s;
 }
 
-int size_class(int64_t pair_elems) {
+int size_class(int64_t v) {
   int c = 0;
-  while ((int64_t(1) << (c + 1)) <= pair_elems) ++c;
+  while ((int64_t(1) << (c + 1)) <= v) ++c;
   return c;
 }
 
-int64_t Tuning::item_elems_for(int64_t pair_elems, int fp32) const {  // pair_elems: launch total
-  auto it = table.find({fp32, size_class(pair_elems)});
+int64_t Tuning::item_elems_for(int64_t elems, int npairs, int fp32) const {  // launch totals
+  auto it = table.find(tune_key(fp32, elems, npairs));
   if (it != table.end()) return it->second.item_elems;
-  return std::max<int64_t>(2048, std::min<int64_t>(item_elems, pair_elems / std::max<int64_t>(1, min_items)));
+  return std::max<int64_t>(2048, std::min<int64_t>(item_elems, elems / std::max<int64_t>(1, min_items)));
 }
 
-int Tuning::unroll_for(int64_t elems, int fp32) const {
-  auto it = table.find({fp32, size_class(elems)});
+int Tuning::unroll_for(int64_t elems, int npairs, int fp32) const {
+  auto it = table.find(tune_key(fp32, elems, npairs));
   return it != table.end() ? it->second.unroll : unroll;
 }
 
-int Tuning::vec_per_lane_for(int64_t elems, int fp32) const {
-  auto it = table.find({fp32, size_class(elems)});
+int Tuning::vec_per_lane_for(int64_t elems, int npairs, int fp32) const {
+  auto it = table.find(tune_key(fp32, elems, npairs));
   return it != table.end() ? it->second.vec_per_lane : vec_per_lane;
 }
 
@@ -121,7 +121,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   // workgroup size of the slab pass: enough workgroups to fill the chip,
   // never more than item_elems elements each (or the autotuned size for
   // this total)
-  const int64_t item_elems = tune.item_elems_for(total, fp32);
+  const int npairs = (int)shapes.size();
+  const int64_t item_elems = tune.item_elems_for(total, npairs, fp32);
   int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0, taboff = 0;
   int maxvpl = 1;
   for (size_t p = 0; p < shapes.size(); ++p) {
@@ -139,7 +140,7 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       const int Q = F.P / W;
       // about two 16-byte vectors per lane per row: short DPP trees for the
       // row sums, few column accumulators per lane
-      const int vt = tune.vec_per_lane_for(total, fp32);
+      const int vt = tune.vec_per_lane_for(total, npairs, fp32);
       const int LR = std::min(64, next_pow2((Q + vt - 1) / vt));
       const int vpl = (Q + LR - 1) / LR;
       F.lrs = ilog2(LR);
@@ -816,7 +817,7 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
     int64_t total = 0;
     for (int p = 0; p < count; ++p)
       total += (int64_t)probs[p].m * probs[p].m * probs[p].n + (int64_t)probs[p].m * probs[p].n * probs[p].n;
-    ws->args.unroll = ctx->tune.unroll_for(total, prec == HOT_FP32_STREAM);
+    ws->args.unroll = ctx->tune.unroll_for(total, count, prec == HOT_FP32_STREAM);
   }
   ws->args.slab_grid = ws->args.nitems;
   ws->args.nt_store = ctx->tune.nt_store;

@@ -1,6 +1,6 @@
 // HIP kernels of the HOT iteration (arXiv 2408.00598, Algorithm 2) for gfx950.
 //
-// One iteration is three launches:
+// One iteration is three launches (the first in hot_slab.hip):
 //   k_slab_pass   streams every slab of the flow state once (Steps 2-4 fused:
 //                 g = c - A^T ybar, shat = |s - 2g|, Halpern step) and produces
 //                 the row / column sums of the new state (the A s of Step 1 of
@@ -13,6 +13,7 @@
 //                 alpha / beta vectors the next slab pass reads.
 // Reductions have a fixed order (no floating-point atomics), so a problem
 // gives bit-identical results alone or inside a batch.
+#include "hot_device.h"
 #include "hot_internal.h"
 #include "hot_runtime.h"
 
@@ -20,318 +21,7 @@
 
 namespace hot {
 
-template <typename T>
-struct VecT;
-template <>
-struct VecT<float> {
-  static constexpr int W = 4;
-  typedef float4 type;
-  typedef float native __attribute__((ext_vector_type(4)));
-};
-template <>
-struct VecT<double> {
-  static constexpr int W = 2;
-  typedef double2 type;
-  typedef double native __attribute__((ext_vector_type(2)));
-};
-
-__device__ inline float vget(const float4& v, int e) {
-  return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
-}
-__device__ inline double vget(const double2& v, int e) { return e == 0 ? v.x : v.y; }
-__device__ inline void vset(float4& v, int e, float x) {
-  if (e == 0) v.x = x; else if (e == 1) v.y = x; else if (e == 2) v.z = x; else v.w = x;
-}
-__device__ inline void vset(double2& v, int e, double x) {
-  if (e == 0) v.x = x; else v.y = x;
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum over the 256 threads of a block, fixed order; every thread gets it.
-__device__ inline double block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int wave = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[wave] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-template <typename T>
-__device__ inline T* pick(T* b0, T* b1, T* b2, int i) {
-  return i == 0 ? b0 : (i == 1 ? b1 : b2);
-}
-
-// ---------------------------------------------------------------------------
-// Slab pass.  One workgroup per (slab, row chunk).  A row of the slab is
-// covered by LR = 2^lrs lanes, each holding vpl 16-byte vectors of the row;
-// a wave covers 64/LR rows per step, the four waves interleave, and two
-// steps are loaded before either is computed.  Column sums stay in FP64
-// registers for the whole chunk; row sums are finished with DPP moves inside
-// the wave (the sum lands in the last lane of each LR-lane group).
-// The pass is specialised at compile time on its mode and on where the
-// Halpern anchor comes from, so the element loop has no branches.
-// ---------------------------------------------------------------------------
-template <int CTRL, int RM = 0xf>
-__device__ inline double dpp_mov(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  int lo = (int)b, hi = (int)(b >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xf, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// Sum over aligned groups of LR lanes (LR a power of two <= 64); valid in
-// the last lane of each group.
-__device__ inline double group_sum(double v, int LR) {
-  if (LR >= 2) v += dpp_mov<0xB1>(v);        // quad_perm [1,0,3,2]
-  if (LR >= 4) v += dpp_mov<0x4E>(v);        // quad_perm [2,3,0,1]
-  if (LR >= 8) v += dpp_mov<0x141>(v);       // row_half_mirror
-  if (LR >= 16) v += dpp_mov<0x140>(v);      // row_mirror
-  if (LR >= 32) v += dpp_mov<0x142, 0xA>(v); // row_bcast:15 into rows 1, 3
-  if (LR >= 64) v += dpp_mov<0x143, 0xC>(v); // row_bcast:31 into rows 2, 3
-  return v;
-}
-
-enum { ANC_ZERO = 0, ANC_SAME = 1, ANC_SEP = 2 };
-
-struct SlabCtx {
-  int L, P, r0, r1, lrs, vpl, lin, slot, wave, lane;
-  double lam, oml, sigma;
-};
-
-template <typename T, int MAXVPL, int MODE, int ANC, int U, int C>
-__device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
-                                 T* __restrict__ dst, const T* __restrict__ anc,
-                                 const double* __restrict__ alpha, const double* __restrict__ bl,
-                                 const double* __restrict__ lx,
-                                 double (&colacc)[MAXVPL][VecT<T>::W], double* __restrict__ rowsum,
-                                 double (&kk)[6]) {
-  constexpr int W = VecT<T>::W;
-  typedef typename VecT<T>::type VT;
-  const int LR = 1 << x.lrs, rpw = 64 >> x.lrs;
-  const int L = x.L, P = x.P;
-  constexpr int UR = U & 3;
-  for (int pb = x.r0 + x.wave * rpw; pb < x.r1; pb += 4 * UR * rpw) {
-    int prow[UR];
-    bool rvv[UR];
-    VT xs[UR][MAXVPL], xa[UR][MAXVPL];
-#pragma unroll
-    for (int u = 0; u < UR; ++u) {
-      prow[u] = pb + u * 4 * rpw + x.slot;
-      rvv[u] = prow[u] < x.r1;
-#pragma unroll
-      for (int v = 0; v < MAXVPL; ++v) {
-        const int q0 = (x.lin + (v << x.lrs)) * W;
-        if (v < x.vpl && rvv[u] && q0 < L) {
-          xs[u][v] = *reinterpret_cast<const VT*>(src + (int64_t)prow[u] * P + q0);
-          if (ANC == ANC_SEP) xa[u][v] = *reinterpret_cast<const VT*>(anc + (int64_t)prow[u] * P + q0);
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < UR; ++u) {
-      const int p = prow[u];
-      const bool rv = rvv[u];
-      const double ap = rv ? alpha[p] : 0.0;
-      const double xp = (C && rv) ? lx[p] : 0.0;  // row position (non-uniform bins)
-      double rowacc = 0.0;
-#pragma unroll
-      for (int v = 0; v < MAXVPL; ++v) {
-        const int q0 = (x.lin + (v << x.lrs)) * W;
-        if (v < x.vpl && rv && q0 < L) {
-          VT out;
-          const double d0 = (double)(p - q0);
-#pragma unroll
-          for (int e = 0; e < W; ++e) {
-            const bool ok = (q0 + e) < L;
-            const double s = (double)vget(xs[u][v], e);
-            const double d = C ? xp - lx[q0 + e] : d0 - (double)e;
-            const double g = d * d - (ap + bl[q0 + e]);
-            double o;
-            if (MODE == MODE_RESTART) {
-              o = fmax(s - g, g);
-            } else {
-              const double sh = fabs(s - 2.0 * g);
-              if (ANC == ANC_ZERO) o = x.oml * sh;
-              else if (ANC == ANC_SAME) o = x.lam * s + x.oml * sh;
-              else o = x.lam * (double)vget(xa[u][v], e) + x.oml * sh;
-              if (MODE == MODE_CHECK) {
-                const double xb = x.sigma * (s - g);
-                const double zb = fmax(0.0, 2.0 * g - s);
-                const double dr = zb - g;
-                const double mn = fmin(xb, zb);
-                const double fr = s - sh;
-                kk[KI_DUAL] += ok ? dr * dr : 0.0;
-                kk[KI_COMP] += ok ? mn * mn : 0.0;
-                kk[KI_XX] += ok ? xb * xb : 0.0;
-                kk[KI_ZZ] += ok ? zb * zb : 0.0;
-                kk[KI_CX] += ok ? d * d * xb : 0.0;
-                kk[KI_FP] += ok ? fr * fr : 0.0;
-              }
-            }
-            const T st = ok ? (T)o : (T)0;
-            const double sd = (double)st;
-            rowacc += sd;
-            colacc[v][e] += sd;
-            vset(out, e, st);
-          }
-          if (U & 4)
-            __builtin_nontemporal_store(
-                __builtin_bit_cast(typename VecT<T>::native, out),
-                reinterpret_cast<typename VecT<T>::native*>(dst + (int64_t)p * P + q0));
-          else
-            *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
-        }
-      }
-      rowacc = group_sum(rowacc, LR);
-      if (rv && x.lin == LR - 1) rowsum[p] = rowacc;
-    }
-  }
-}
-
-// HEAVY = 0: plain update passes; HEAVY = 1: check and restart passes.  Both
-// kernels are launched every iteration; a workgroup whose pair is in the
-// other kind of pass exits at once.
-template <typename T, int MAXVPL, int HEAVY, int U, int C>
-__device__ inline void slab_item(
-    int item, const SlabItem* __restrict__ items, const PairGeo* __restrict__ geo,
-    const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
-    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
-    double* __restrict__ colpart, double* __restrict__ kitem,
-    unsigned long long* __restrict__ bytes_ctr, double* lds_col, double* lds_beta, double* lds_x,
-    double* red) {
-  constexpr int W = VecT<T>::W;
-  constexpr int S = 64 * MAXVPL * W;
-  const SlabItem itm = items[item];
-  const PairCtl* cp = ctl + itm.pair;
-  const int status = cp->status;
-  const int mode = cp->mode;
-  if (status != ST_RUNNING) return;
-  if (HEAVY ? (mode != MODE_CHECK && mode != MODE_RESTART) : (mode != MODE_NORMAL)) return;
-  // (uniform per workgroup: every thread reads the same control block)
-  const FamGeo F = geo[itm.pair].f[itm.fam];
-  SlabCtx x;
-  x.L = F.L;
-  x.P = F.P;
-  x.r0 = itm.chunk * F.rpc;
-  x.r1 = min(F.L, x.r0 + F.rpc);
-  x.lrs = F.lrs;
-  x.vpl = F.vpl;
-  x.lane = threadIdx.x & 63;
-  x.wave = threadIdx.x >> 6;
-  x.slot = x.lane >> x.lrs;
-  x.lin = x.lane & ((1 << x.lrs) - 1);
-  x.lam = cp->lam;
-  x.oml = 1.0 - cp->lam;
-  x.sigma = cp->sigma;
-  const int L = F.L;
-  const int64_t soff = F.soff + (int64_t)itm.slab * L * F.P;
-  const int src_i = cp->src, anc_i = cp->anc;
-  const int dst_i = (mode == MODE_RESTART) ? 2 : cp->dst;
-  const T* src = pick<T>(sb0, sb1, sb2, src_i) + soff;
-  T* dst = pick<T>(sb0, sb1, sb2, dst_i) + soff;
-  const int anc_kind =
-      (mode == MODE_RESTART || anc_i < 0) ? ANC_ZERO : (anc_i == src_i ? ANC_SAME : ANC_SEP);
-  const T* anc = anc_kind == ANC_SEP ? pick<T>(sb0, sb1, sb2, anc_i) + soff : src;
-  const double* alpha = ab + F.aboff + (int64_t)itm.slab * 2 * L;
-  const double* beta = alpha + L;
-  double* rs = rowsum + F.rsoff + (int64_t)itm.slab * L;
-  // beta in LDS (zero in the padding columns); the barrier also keeps the
-  // previous item's readers of lds_col / lds_beta behind us
-  __syncthreads();
-  for (int q = threadIdx.x; q < F.P; q += kWG) lds_beta[q] = q < L ? beta[q] : 0.0;
-  if (C) {
-    const double* X = fam_x(ab, F);
-    for (int q = threadIdx.x; q < F.P; q += kWG) lds_x[q] = q < L ? X[q] : 0.0;
-  }
-  __syncthreads();
-
-  double colacc[MAXVPL][W];
-#pragma unroll
-  for (int v = 0; v < MAXVPL; ++v)
-#pragma unroll
-    for (int e = 0; e < W; ++e) colacc[v][e] = 0.0;
-  double kk[6] = {0, 0, 0, 0, 0, 0};
-  if (!HEAVY) {
-    if (anc_kind == ANC_ZERO)
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else if (anc_kind == ANC_SAME)
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SAME, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SEP, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-  } else if (mode == MODE_CHECK) {
-    if (anc_kind == ANC_ZERO)
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else if (anc_kind == ANC_SAME)
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SAME, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SEP, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-  } else {
-    slab_rows<T, MAXVPL, MODE_RESTART, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-  }
-
-  // column partials: fold the row slots of the wave, then the four waves
-  const int LR = 1 << x.lrs;
-#pragma unroll
-  for (int v = 0; v < MAXVPL; ++v)
-#pragma unroll
-    for (int e = 0; e < W; ++e) {
-      double t = colacc[v][e];
-      for (int off = LR; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
-      colacc[v][e] = t;
-    }
-  if (x.slot == 0) {
-#pragma unroll
-    for (int v = 0; v < MAXVPL; ++v)
-#pragma unroll
-      for (int e = 0; e < W; ++e) {
-        const int q = ((x.lin + (v << x.lrs)) * W) + e;
-        if (v < x.vpl && q < L) lds_col[x.wave * S + q] = colacc[v][e];
-      }
-  }
-  __syncthreads();
-  double* cpo = colpart + F.cpoff + ((int64_t)itm.slab * F.nchunk + itm.chunk) * L;
-  for (int q = threadIdx.x; q < L; q += kWG)
-    cpo[q] = (lds_col[q] + lds_col[S + q]) + (lds_col[2 * S + q] + lds_col[3 * S + q]);
-  if (threadIdx.x == 0 && bytes_ctr) {
-    // algorithmic stream traffic of this item: read s (and the anchor when it
-    // is a separate buffer), write the new state
-    const int streams = anc_kind == ANC_SEP ? 3 : 2;
-    atomicAdd(bytes_ctr, (unsigned long long)(x.r1 - x.r0) * L * sizeof(T) * streams);
-  }
-  if (HEAVY && mode == MODE_CHECK) {
-    double* ko = kitem + (int64_t)item * kKI;
-    double r[6];
-    for (int q = 0; q < 6; ++q) r[q] = block_sum(kk[q], red);
-    if (threadIdx.x == 0)
-      for (int q = 0; q < 6; ++q) ko[q] = r[q];
-  }
-}
-
-// One workgroup per item.
-template <typename T, int MAXVPL, int HEAVY, int U, int C>
-__global__ __launch_bounds__(kWG) void k_slab_pass(
-    const SlabItem* __restrict__ items, int nitems, const PairGeo* __restrict__ geo,
-    const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
-    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
-    double* __restrict__ colpart, double* __restrict__ kitem,
-    unsigned long long* __restrict__ bytes_ctr) {
-  constexpr int W = VecT<T>::W;
-  constexpr int S = 64 * MAXVPL * W;
-  __shared__ double lds_col[4 * S];
-  __shared__ double lds_beta[S];
-  __shared__ double lds_x[C ? S : 1];
-  __shared__ double red[4];
-  if ((int)blockIdx.x < nitems)
-    slab_item<T, MAXVPL, HEAVY, U, C>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, ab, rowsum,
-                                      colpart, kitem, bytes_ctr, lds_col, lds_beta, lds_x, red);
-}
+void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Pair reduce: R = b/sigma - A(s - c) from the slab sums, the totals the
@@ -1061,50 +751,6 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 // ---------------------------------------------------------------------------
 // Host-side launchers (C++ linkage inside the library).
 // ---------------------------------------------------------------------------
-
-
-template <typename T, int V, int U, int C>
-static void launch_lean(const LaunchArgs& a, int par, hipStream_t st) {
-  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U, C>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                     a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
-                     a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
-}
-
-template <typename T, int V>
-static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
-  if (a.coord) {  // non-uniform bins: positions from LDS, one row per wave step
-    if (a.nt_store) launch_lean<T, V, 5, 1>(a, par, st);
-    else launch_lean<T, V, 1, 1>(a, par, st);
-    hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
-                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
-    return;
-  }
-  const int u = (a.unroll >= 2 ? 2 : 1) | (a.nt_store ? 4 : 0);
-  switch (u) {
-    case 1: launch_lean<T, V, 1, 0>(a, par, st); break;
-    case 2: launch_lean<T, V, 2, 0>(a, par, st); break;
-    case 5: launch_lean<T, V, 5, 0>(a, par, st); break;
-    default: launch_lean<T, V, 6, 0>(a, par, st); break;
-  }
-  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, 0>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                     a.nitems, a.geo,
-                     a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab, a.rowsum[par],
-                     a.colpart[par], a.kitem, a.bytes_ctr);
-}
-
-template <typename T>
-static void launch_slab_t(const LaunchArgs& a, int par, hipStream_t st) {
-  if (a.maxvpl <= 1) launch_slab<T, 1>(a, par, st);
-  else if (a.maxvpl <= 2) launch_slab<T, 2>(a, par, st);
-  else if (a.maxvpl <= 4) launch_slab<T, 4>(a, par, st);
-  else launch_slab<T, 8>(a, par, st);
-}
-
-void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st) {
-  if (a.fp32) launch_slab_t<float>(a, par, st);
-  else launch_slab_t<double>(a, par, st);
-}
 
 void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,

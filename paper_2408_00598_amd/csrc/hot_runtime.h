@@ -6,6 +6,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -24,21 +25,27 @@ struct Tuning {
   int vec_per_lane;     // target 16-byte vectors per lane per slab row (2 or 4)
   int nt_store;         // non-temporal stores of the new state
   int pingpong;         // never update the state in place (read one buffer, write the other)
-  // autotuned elements per workgroup, keyed by (precision, log2 of the
-  // launch's flow elements); overrides the rule above for that size class
+  // autotuned launch shapes, keyed by (precision, floor(log2) of the
+  // launch's flow elements, floor(log2) of its pair count): one large pair
+  // and a batch of small ones of the same total get separate entries
   struct Choice {
     int64_t item_elems;
     int unroll;
     int vec_per_lane;
   };
-  std::map<std::pair<int, int>, Choice> table;
-  // elements per slab-pass workgroup for a launch over `elems` flow elements
-  int64_t item_elems_for(int64_t elems, int fp32) const;
-  int unroll_for(int64_t elems, int fp32) const;
-  int vec_per_lane_for(int64_t elems, int fp32) const;
+  typedef std::tuple<int, int, int> Key;
+  std::map<Key, Choice> table;
+  // elements per slab-pass workgroup for a launch of `npairs` problems over
+  // `elems` flow elements
+  int64_t item_elems_for(int64_t elems, int npairs, int fp32) const;
+  int unroll_for(int64_t elems, int npairs, int fp32) const;
+  int vec_per_lane_for(int64_t elems, int npairs, int fp32) const;
 };
 Tuning default_tuning();
-int size_class(int64_t pair_elems);
+int size_class(int64_t v);  // floor(log2(v)) for v >= 1
+inline Tuning::Key tune_key(int fp32, int64_t elems, int npairs) {
+  return Tuning::Key{fp32, size_class(elems), size_class(npairs)};
+}
 
 struct LaunchArgs {
   const SlabItem* items = nullptr;

@@ -64,8 +64,8 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
     p.coord_row = nullptr;  // the uniform grid (the launch shape does not
     p.coord_col = nullptr;  // depend on the positions)
   }
-  const int cls = size_class(total);
-  const std::pair<int, int> key{prec == HOT_FP32_STREAM, cls};
+  const int cls = size_class(total), pcls = size_class(count);
+  const Tuning::Key key = tune_key(prec == HOT_FP32_STREAM, total, count);
   const Tuning saved = ctx->tune;
   double best = 1e300, dflt = 0.0;
   Tuning::Choice bestc{0, 1, 4};
@@ -111,10 +111,11 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
     FILE* f = std::fopen(cache_path, "a");
     if (f) {
       std::fprintf(f,
-                   "{\"arch\": \"%s\", \"fp32\": %d, \"size_class\": %d, \"item_elems\": %lld, "
-                   "\"unroll\": %d, \"vec_per_lane\": %d, \"slab_us_per_iter\": %.3f, "
-                   "\"default_us_per_iter\": %.3f}\n",
-                   arch_name(ctx->device).c_str(), key.first, cls, (long long)bestc.item_elems,
+                   "{\"arch\": \"%s\", \"fp32\": %d, \"size_class\": %d, \"pairs_class\": %d, "
+                   "\"item_elems\": %lld, \"unroll\": %d, \"vec_per_lane\": %d, "
+                   "\"slab_us_per_iter\": %.3f, \"default_us_per_iter\": %.3f}\n",
+                   arch_name(ctx->device).c_str(), std::get<0>(key), cls, pcls,
+                   (long long)bestc.item_elems,
                    bestc.unroll, bestc.vec_per_lane, best * 1e6, dflt * 1e6);
       std::fclose(f);
     }
@@ -138,15 +139,15 @@ extern "C" hot_status hot_autotune_load(hot_ctx* ctx, const char* cache_path) {
   int loaded = 0;
   while (std::fgets(line, sizeof(line), f)) {
     char a[64] = {0};
-    int fp32 = 0, cls = 0, u = 1, v = 4;
+    int fp32 = 0, cls = 0, pcls = 0, u = 1, v = 4;
     long long e = 0;
     if (std::sscanf(line,
-                    "{\"arch\": \"%63[^\"]\", \"fp32\": %d, \"size_class\": %d, \"item_elems\": "
-                    "%lld, \"unroll\": %d, \"vec_per_lane\": %d",
-                    a, &fp32, &cls, &e, &u, &v) == 6 &&
+                    "{\"arch\": \"%63[^\"]\", \"fp32\": %d, \"size_class\": %d, \"pairs_class\": "
+                    "%d, \"item_elems\": %lld, \"unroll\": %d, \"vec_per_lane\": %d",
+                    a, &fp32, &cls, &pcls, &e, &u, &v) == 7 &&
         arch == a && e >= 1024 && (u == 1 || u == 2) && (v == 2 || v == 4)) {
       std::lock_guard<std::mutex> lk(ctx->mu);
-      ctx->tune.table[{fp32, cls}] = Tuning::Choice{(int64_t)e, u, v};  // later lines win
+      ctx->tune.table[Tuning::Key{fp32, cls, pcls}] = Tuning::Choice{(int64_t)e, u, v};  // later lines win
       ++loaded;
     }
   }
