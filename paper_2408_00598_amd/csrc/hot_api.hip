@@ -169,7 +169,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
         for (int c = 0; c < F.nchunk; ++c) lay.items.push_back(SlabItem{(int32_t)p, fam, s, c});
     }
     g.nitem = (int32_t)lay.items.size() - g.item0;
-    g.nblk = (std::max(m, n) + 3) / 4;  // reduce row blocks: rows 4b..4b+3 of each family
+    g.nb1 = (n + 3) / 4;                // reduce row blocks: rows j = 4b..4b+3 of F1,
+    g.nblk = g.nb1 + (m + 3) / 4;       // then rows k = 4b..4b+3 of F2
     g.ns1 = (m + 63) / 64;              // reduce strips over the columns k of rs1
     g.ns2 = (n + 63) / 64;              // reduce strips over the columns j of rs2
     g.nsblk = (m + n + 3) / 4;          // solve row blocks: slabs 4b..4b+3
@@ -177,7 +178,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
     g.ntk = (m + 31) / 32;
     g.ipb = (g.nitem + g.nblk - 1) / g.nblk;
     g.blk0 = (int32_t)lay.blocks.size();
-    for (int b = 0; b < g.nblk; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 0, 0});
+    for (int b = 0; b < g.nb1; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 0, 0});
+    for (int b = 0; b < g.nblk - g.nb1; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 3, 0});
     for (int b = 0; b < g.ns1; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 1, 0});
     for (int b = 0; b < g.ns2; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 2, 0});
     g.sblk0 = (int32_t)lay.sblocks.size();

@@ -25,14 +25,18 @@ void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Pair reduce: R = b/sigma - A(s - c) from the slab sums, the totals the
-// structured solve needs, and (check passes) the KKT partials.
-//   kind 0, row block b: one wave per row j = 4b + w of R2 (and the total of
-//           row j of the F1 row sums) and per row k = 4b + w of R3^T (and the
-//           total of row k of the F2 row sums);
+// structured solve needs, and (check passes) the KKT partials.  Four block
+// kinds, so that rows of both families run on separate waves:
+//   kind 0, F1 row block b (slot b): one wave per row j = 4b + w of R2 and
+//           the total of row j of the F1 row sums;
+//   kind 3, F2 row block b (slot nb1 + b): one wave per row k = 4b + w of
+//           R3^T and the total of row k of the F2 row sums;
 //   kind 1, strip s: u1[k] = sum_j rs1[j][k] for 64 columns k (lane per column);
 //   kind 2, strip s: u2[j] = sum_k rs2[k][j] for 64 columns j.
-// Every access is along a row.  R1 itself is never stored: the solve reads
-// it straight from the two row-sum arrays, tile by tile.
+// Column sums of a slab arrive as per-chunk partials; they are added with
+// four independent accumulators (fixed order) so the loads overlap.
+// R1 itself is never stored: the solve reads it straight from the two
+// row-sum arrays, tile by tile.
 // With C_L(p) = sum_q (X_p - X_q)^2 and CC_L = sum_p C_L(p) from the family's
 // cost table (X_p = p on the uniform grid):
 //   R1[j][k] = -(rs1[j][k] - C_m(k)) + (rs2[k][j] - C_n(j)),
@@ -40,6 +44,25 @@ void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st);
 //   sum_j R1[j][k] = -(u1[k] - n C_m(k)) + (tot2[k] - CC_n).
 // ---------------------------------------------------------------------------
 __device__ inline double dinv(int m, int k) { return (k == m - 1) ? 1.0 / (m + 1.0) : 1.0 / m; }
+
+// sum_c p[c * stride], c < nchunk, in a fixed order with four accumulators
+__device__ inline double chunk_sum(const double* __restrict__ p, int nchunk, int64_t stride) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int c = 0;
+  for (; c + 4 <= nchunk; c += 4) {
+    a0 += p[(int64_t)c * stride];
+    a1 += p[(int64_t)(c + 1) * stride];
+    a2 += p[(int64_t)(c + 2) * stride];
+    a3 += p[(int64_t)(c + 3) * stride];
+  }
+  for (; c < nchunk; ++c) a0 += p[(int64_t)c * stride];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// block-wide fixed-order totals of q values held by lane 0 of each wave
+__device__ inline double wave4(const double (&w)[4][kKP], int q) {
+  return (w[0][q] + w[1][q]) + (w[2][q] + w[3][q]);
+}
 
 __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const PBlock* __restrict__ blocks, const PairGeo* __restrict__ geo,
@@ -58,16 +81,24 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   const int m = G.m, n = G.n, b = pbk.blk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const FamGeo F1 = G.f[0], F2 = G.f[1];
-  if (pbk.kind != 0) {
+  if (pbk.kind == 1 || pbk.kind == 2) {
     // column totals of a row-sum array: lane = column, waves split the rows
     const bool s1 = pbk.kind == 1;
     const int ncol = s1 ? m : n, nrow = s1 ? n : m;
     const double* rs = s1 ? rowsum + F1.rsoff : rowsum + F2.rsoff;  // [nrow][ncol]
     const int col = 64 * b + lane;
-    double acc = 0.0;
-    if (col < ncol)
-      for (int r = wave; r < nrow; r += 4) acc += rs[(int64_t)r * ncol + col];
-    strip[wave][lane] = acc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (col < ncol) {
+      int r = wave;
+      for (; r + 12 < nrow; r += 16) {
+        a0 += rs[(int64_t)r * ncol + col];
+        a1 += rs[(int64_t)(r + 4) * ncol + col];
+        a2 += rs[(int64_t)(r + 8) * ncol + col];
+        a3 += rs[(int64_t)(r + 12) * ncol + col];
+      }
+      for (; r < nrow; r += 4) a0 += rs[(int64_t)r * ncol + col];
+    }
+    strip[wave][lane] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     if (wave == 0) {
       const double tot = (strip[0][lane] + strip[1][lane]) + (strip[2][lane] + strip[3][lane]);
@@ -88,19 +119,20 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     }
     return;
   }
+  const bool f1 = pbk.kind == 0;
+  const int slot = f1 ? b : G.nb1 + b;
   const double isg = 1.0 / cp->sigma;
   const double* mu1T = arr + arr_mu1T(G);
   const double* mu2 = arr + arr_mu2(G);
-  double* R2 = arr + arr_R2(G);
-  double* R3T = arr + arr_R3T(G);
-  const int j = 4 * b + wave, k = 4 * b + wave;
-  double p_sa = 0.0, p_sp = 0.0, p_u = 0.0;
-  if (j < n) {
+  const int r = 4 * b + wave;  // row j (F1 block) or k (F2 block)
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;  // (sum a_j, sum PR3, sum Sp / D) partials
+  if (f1 && r < n) {
+    const int j = r;
+    double* R2 = arr + arr_R2(G);
     double sr2 = 0.0, t1 = 0.0;
     const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
     for (int i = lane; i < m; i += 64) {
-      double cs = 0.0;
-      for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m + i];
+      const double cs = chunk_sum(cpj + i, F1.nchunk, m);
       const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - fam_cr(ab, F1, i));
       R2[(int64_t)j * m + i] = r2;
       sr2 += r2;
@@ -112,16 +144,16 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       vec[vec_a(G) + j] = sr2;
       vec[vec_tot1(G) + j] = t1;
     }
-    p_sa = sr2;
-  }
-  if (k < m) {
+    p0 = sr2;
+  } else if (!f1 && r < m) {
+    const int k = r;
+    double* R3T = arr + arr_R3T(G);
     double s3 = 0.0, t2 = 0.0;
     const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
     for (int l = lane; l < n; l += 64) {
       double r3 = 0.0;
       if (!(k == m - 1 && l == n - 1)) {
-        double cs = 0.0;
-        for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n + l];
+        const double cs = chunk_sum(cpk + l, F2.nchunk, n);
         r3 = mu2[(int64_t)k * n + l] * isg - (cs - fam_cr(ab, F2, l));
       }
       R3T[(int64_t)k * n + l] = r3;
@@ -134,25 +166,23 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       vec[vec_PR3(G) + k] = s3;
       vec[vec_tot2(G) + k] = t2;
     }
-    p_sp = s3;
-    p_u = ((t2 - fam_cc(ab, F2)) + s3) * dinv(m, k);
+    p1 = s3;
+    p2 = ((t2 - fam_cc(ab, F2)) + s3) * dinv(m, k);
   }
   if (lane == 0) {
-    wred[wave][0] = p_sa;
-    wred[wave][1] = p_sp;
-    wred[wave][2] = p_u;
+    wred[wave][0] = p0;
+    wred[wave][1] = p1;
+    wred[wave][2] = p2;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
-    const int q = threadIdx.x;
-    vec[vec_spart(G) + 4 * (int64_t)b + q] = (wred[0][q] + wred[1][q]) + (wred[2][q] + wred[3][q]);
-  }
+  if (threadIdx.x < 3)
+    vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
   if (mode != MODE_CHECK) return;
 
   // ---- check pass: KKT partials of w_bar^k -------------------------------
   double part[kKI] = {0, 0, 0, 0, 0, 0, 0, 0};
   {
-    const int i0 = G.item0 + b * G.ipb;
+    const int i0 = G.item0 + slot * G.ipb;
     const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
     for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
       for (int q = 0; q < 6; ++q) part[q] += kitem[(int64_t)it * kKI + q];
@@ -162,7 +192,8 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   // alpha, beta and their per-slab totals.
   const double sg = cp->sigma;
   double prim = 0.0, by = 0.0;
-  if (j < n) {
+  if (f1 && r < n) {
+    const int j = r;
     const double* al = ab + F1.aboff + (int64_t)j * 2 * m;
     const double* be = al + m;
     const double sa = ab[F1.sumoff + 2 * (int64_t)j], sb = ab[F1.sumoff + 2 * (int64_t)j + 1];
@@ -174,31 +205,29 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
                               (fam_cr(ab, F1, kk) - m * al[kk] - sb));
       const double x2 = sg * (rowsum_prev[F2.rsoff + (int64_t)kk * n + j] -
                               (fam_cr(ab, F2, j) - n * al2[j] - sb2));
-      const double r = x1 - x2;
-      prim += r * r;
+      const double rr = x1 - x2;
+      prim += rr * rr;
     }
     const double* cpj = colpart_prev + F1.cpoff + (int64_t)j * F1.nchunk * m;
     for (int i = lane; i < m; i += 64) {
-      double cs = 0.0;
-      for (int c = 0; c < F1.nchunk; ++c) cs += cpj[(int64_t)c * m + i];
+      const double cs = chunk_sum(cpj + i, F1.nchunk, m);
       const double x = sg * (cs - (fam_cr(ab, F1, i) - sa - m * be[i]));
-      const double r = x - mu1T[(int64_t)j * m + i];
-      prim += r * r;
+      const double rr = x - mu1T[(int64_t)j * m + i];
+      prim += rr * rr;
       by += mu1T[(int64_t)j * m + i] * be[i];
     }
-  }
-  if (k < m) {
+  } else if (!f1 && r < m) {
+    const int k = r;
     const double* al = ab + F2.aboff + (int64_t)k * 2 * n;
     const double* be = al + n;
     const double sa = ab[F2.sumoff + 2 * (int64_t)k];
     const double* cpk = colpart_prev + F2.cpoff + (int64_t)k * F2.nchunk * n;
     for (int l = lane; l < n; l += 64) {
       if (k == m - 1 && l == n - 1) continue;
-      double cs = 0.0;
-      for (int c = 0; c < F2.nchunk; ++c) cs += cpk[(int64_t)c * n + l];
+      const double cs = chunk_sum(cpk + l, F2.nchunk, n);
       const double x = sg * (cs - (fam_cr(ab, F2, l) - sa - n * be[l]));
-      const double r = x - mu2[(int64_t)k * n + l];
-      prim += r * r;
+      const double rr = x - mu2[(int64_t)k * n + l];
+      prim += rr * rr;
       by += mu2[(int64_t)k * n + l] * be[l];
     }
   }
@@ -210,10 +239,8 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     if (lane == 0) wred[wave][q] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 8) {
-    const int q = threadIdx.x;
-    vec[vec_kpart(G) + (int64_t)b * kKP + q] = (wred[0][q] + wred[1][q]) + (wred[2][q] + wred[3][q]);
-  }
+  if (threadIdx.x < 8)
+    vec[vec_kpart(G) + (int64_t)slot * kKP + threadIdx.x] = wave4(wred, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -697,21 +724,24 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
                                                           const PairGeo* __restrict__ geo,
                                                           const double* __restrict__ arr,
                                                           double* __restrict__ vec) {
-  __shared__ double wred[4][4];
+  __shared__ double wred[4][kKP];
   const PBlock pbk = blocks[blockIdx.x];
   const PairGeo G = geo[pbk.pair];
   const int m = G.m, n = G.n, b = pbk.blk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (pbk.kind != 0) {  // strip slots carry no partial on this path
+  if (pbk.kind == 1 || pbk.kind == 2) {  // strip slots carry no partial on this path
     if (pbk.kind == 1 && threadIdx.x < 4) vec[vec_spart(G) + 4 * (int64_t)(G.nblk + b) + threadIdx.x] = 0.0;
     return;
   }
+  const bool f1 = pbk.kind == 0;
+  const int slot = f1 ? b : G.nb1 + b;
   const double* R1 = arr + arr_R1(G);
   const double* R2 = arr + arr_R2(G);
   const double* R3T = arr + arr_R3T(G);
-  const int j = 4 * b + wave, k = 4 * b + wave;
-  double p_sa = 0.0, p_sp = 0.0, p_u = 0.0;
-  if (j < n) {
+  const int r = 4 * b + wave;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  if (f1 && r < n) {
+    const int j = r;
     double s1 = 0.0, s2 = 0.0;
     for (int kk = lane; kk < m; kk += 64) s1 += R1[(int64_t)j * m + kk];
     for (int i = lane; i < m; i += 64) s2 += R2[(int64_t)j * m + i];
@@ -721,9 +751,9 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
       vec[vec_b1(G) + j] = s1;
       vec[vec_a(G) + j] = s2;
     }
-    p_sa = s2;
-  }
-  if (k < m) {
+    p0 = s2;
+  } else if (!f1 && r < m) {
+    const int k = r;
     double s3 = 0.0, c1 = 0.0;
     for (int l = lane; l < n; l += 64) s3 += R3T[(int64_t)k * n + l];
     for (int jj = lane; jj < n; jj += 64) c1 += R1[(int64_t)jj * m + k];
@@ -733,19 +763,17 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
       vec[vec_PR3(G) + k] = s3;
       vec[vec_Sp(G) + k] = c1 + s3;
     }
-    p_sp = s3;
-    p_u = (c1 + s3) * dinv(m, k);
+    p1 = s3;
+    p2 = (c1 + s3) * dinv(m, k);
   }
   if (lane == 0) {
-    wred[wave][0] = p_sa;
-    wred[wave][1] = p_sp;
-    wred[wave][2] = p_u;
+    wred[wave][0] = p0;
+    wred[wave][1] = p1;
+    wred[wave][2] = p2;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
-    const int q = threadIdx.x;
-    vec[vec_spart(G) + 4 * (int64_t)b + q] = (wred[0][q] + wred[1][q]) + (wred[2][q] + wred[3][q]);
-  }
+  if (threadIdx.x < 3)
+    vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
