@@ -85,7 +85,7 @@ typedef struct {
                               (u_i, v_j) and the ground cost is the squared
                               distance (u_i-u_k)^2 + (v_j-v_l)^2: the
                               non-uniform bins of the color-transfer
-                              application (Sec. 5.3); A and b are unchanged,
+                              application (Sec. 4.2); A and b are unchanged,
                               only c (eq. def:c) follows the positions.
                               Positions need not be sorted or distinct. */
 } hot_problem;

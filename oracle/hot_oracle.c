@@ -42,7 +42,7 @@ void or_dims(int32_t m, int32_t n, int64_t *N, int64_t *M3) {
  * c1_{i,k,j} = (u_k - u_i)^2, c2_{k,j,l} = (v_j - v_l)^2.  The squared
  * Euclidean distance between bins (i,j) and (k,l) splits into these two
  * terms for any such (possibly non-uniform) grid, which is what the
- * color-transfer application's K-means grid lines use (Sec. 5.3).
+ * color-transfer application's K-means grid lines use (Sec. 4.2).
  * u == NULL means u_i = i, v == NULL means v_j = j (the uniform grid). */
 void or_cost_xy(int32_t m, int32_t n, const double *u, const double *v, double *c) {
   for (int32_t j = 0; j < n; ++j)

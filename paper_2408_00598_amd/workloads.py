@@ -156,7 +156,7 @@ def serving_pair(n: int, seed: int):
 def grid_lines(L: int, rng, spread: float = 0.7) -> np.ndarray:
     """Sorted, unevenly spaced positions of L grid lines spanning [0, L-1],
     as when lines are drawn through clustered K-means centroids (the
-    non-uniform bins of the color-transfer application, Sec. 5.3): gaps are
+    non-uniform bins of the color-transfer application, Sec. 4.2): gaps are
     Gamma(spread)-distributed, so some lines bunch up and others are far
     apart."""
     if L == 1:

@@ -1,5 +1,5 @@
 """Oracle pins for non-uniform bins: a grid whose rows sit at u_i and columns
-at v_j (the K-means grid lines of the color-transfer application, Sec. 5.3).
+at v_j (the K-means grid lines of the color-transfer application, Sec. 4.2).
 The reduced model only changes through c; A and b are the same.
 
 Pins: HiGHS on the full OT LP with the Euclidean cost of the non-uniform
