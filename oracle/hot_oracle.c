@@ -291,7 +291,11 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   /* sigma = ||b||/||c||; on a 1 x 1 grid every cost is zero and the ratio is
    * undefined, so sigma = 1 there. */
   const double nb = nrm2(M3, b), nc = nrm2(N, c);
-  const double sigma = p->sigma > 0 ? p->sigma : ((nc > 0 && nb > 0) ? nb / nc : 1.0);
+  double sigma = p->sigma > 0 ? p->sigma : ((nc > 0 && nb > 0) ? nb / nc : 1.0);
+  /* optional re-balancing of sigma at restarts: x_bar and y_bar of the last
+   * restart (the initial point 0 before the first) */
+  double *Xr = p->sigma_update ? (double *)calloc((size_t)N, sizeof(double)) : NULL;
+  double *Yr = p->sigma_update ? (double *)calloc((size_t)M3, sizeof(double)) : NULL;
   const int32_t T = p->check_every > 0 ? p->check_every : 1;
   const int32_t fixed = p->fixed_iters > 0 ? p->fixed_iters : 0;
 
@@ -336,6 +340,22 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
             r_prev = r_last;
           } else if (r_last <= 0.2 * r_start ||
                      (r_last <= 0.8 * r_start && r_last > r_prev)) {
+            if (p->sigma_update) {
+              /* primal / dual displacement over the epoch that ends here:
+               * dx = ||x_bar - X||, dy = ||A^T (y_bar - Y)||; the ratio puts
+               * both on the same scale (sigma carries mass / cost units) */
+              double dx2 = 0.0;
+              for (int64_t e = 0; e < N; ++e) {
+                const double d = xbar[e] - Xr[e];
+                dx2 += d * d;
+              }
+              for (int64_t q = 0; q < M3; ++q) R[q] = ybar[q] - Yr[q];
+              or_AT(m, n, R, tmp);
+              const double dy = nrm2(N, tmp), dx = sqrt(dx2);
+              if (dx > 0.0 && dy > 0.0 && isfinite(dx / dy)) sigma = dx / dy;
+              memcpy(Xr, xbar, (size_t)N * sizeof(double));
+              memcpy(Yr, ybar, (size_t)M3 * sizeof(double));
+            }
             memcpy(x, xbar, (size_t)N * sizeof(double));
             memcpy(z, zbar, (size_t)N * sizeof(double));
             memcpy(y, ybar, (size_t)M3 * sizeof(double));
@@ -382,7 +402,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   res->restarts = restarts;
   res->converged = converged;
   free(c); free(b); free(x); free(z); free(y); free(x0); free(z0); free(y0);
-  free(tmp); free(aty); free(R);
+  free(tmp); free(aty); free(R); free(Xr); free(Yr);
   return converged;
 }
 

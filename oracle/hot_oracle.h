@@ -37,6 +37,8 @@ typedef struct {
   int32_t abs_kkt;   /* 1: stop on the absolute residual ||R(w_bar)|| instead of eq. kkt_res */
   const double *coord_row; /* m grid-line positions u_i, or NULL for u_i = i */
   const double *coord_col; /* n grid-line positions v_j, or NULL for v_j = j */
+  int32_t sigma_update; /* 1: at every restart, sigma <- ||x_bar - X|| / ||A^T (y_bar - Y)||
+                           with (X, Y) the w_bar of the previous restart (w^0 = 0 at first) */
 } or_params;
 
 typedef struct {

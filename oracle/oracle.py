@@ -21,7 +21,7 @@ class Params(C.Structure):
                 ("check_every", C.c_int32), ("sigma", C.c_double),
                 ("restart", C.c_int32), ("fixed_iters", C.c_int32),
                 ("admm_rho", C.c_double), ("abs_kkt", C.c_int32),
-                ("coord_row", D), ("coord_col", D)]
+                ("coord_row", D), ("coord_col", D), ("sigma_update", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -153,7 +153,7 @@ def kkt(mu1, mu2, x, y, z, coord_row=None, coord_col=None):
 
 def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
         restart=True, fixed_iters=0, admm_rho=0.0, abs_kkt=False, coord_row=None,
-        coord_col=None):
+        coord_col=None, sigma_update=False):
     """Run Algorithm 2; returns (xbar, ybar, zbar, s_state, result dict)."""
     mu1, mu2 = _f64(mu1), _f64(mu2)
     m, n = mu1.shape
@@ -162,7 +162,7 @@ def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
     yb = np.empty(M3)
     u, v = _coords(m, n, coord_row, coord_col)
     p = Params(tol, max_iter, check_every, sigma, 1 if restart else 0, fixed_iters, admm_rho,
-               1 if abs_kkt else 0, _dn(u), _dn(v))
+               1 if abs_kkt else 0, _dn(u), _dn(v), 1 if sigma_update else 0)
     r = Result()
     lib().or_hot(m, n, _d(mu1), _d(mu2), C.byref(p), _d(xb), _d(yb), _d(zb), _d(s),
                  C.byref(r))

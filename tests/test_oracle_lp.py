@@ -217,3 +217,45 @@ def test_complexity_bound_along_trajectory(oracle, m, n, seed):
         res = oracle.hot(mu1, mu2, fixed_iters=K, restart=False)[4]
         assert res["sigma"] == pytest.approx(sigma, rel=1e-14)
         assert res["kkt_abs"] <= (sigma + 1) / sigma * R0 / (K + 1) * (1 + 1e-9), K
+
+
+@pytest.mark.parametrize("m,n", [(3, 4), (5, 5), (4, 6)])
+def test_sigma_update_reaches_lp_optimum(oracle, m, n):
+    """Optional sigma re-balancing at restarts (sigma <- ||dx|| / ||A^T dy||
+    over the last epoch) still converges to the HiGHS optimum."""
+    rng = np.random.default_rng(7 * m + n)
+    mu1, mu2 = rand_hist(rng, m, n), rand_hist(rng, m, n)
+    Ar, br, cr = reduced_lp(mu1, mu2, oracle)
+    opt, _ = highs(Ar, br, cr)
+    _, _, _, _, res = oracle.hot(mu1, mu2, tol=1e-10, max_iter=400000, sigma_update=True)
+    assert res["converged"] == 1 and res["restarts"] >= 1
+    assert abs(res["primal_obj"] - opt) <= 1e-6 * abs(opt)
+
+
+def test_sigma_update_is_scale_consistent(oracle):
+    """sigma carries mass/cost units: scaling every cost by t (grid positions
+    by sqrt(t)) must scale every sigma by 1/t and leave the iteration count
+    unchanged; the reciprocal rule (||A^T dy|| / ||dx||) would not."""
+    m, n = 6, 7
+    rng = np.random.default_rng(11)
+    mu1, mu2 = rand_hist(rng, m, n), rand_hist(rng, m, n)
+    u, v = np.arange(m, dtype=float), np.arange(n, dtype=float)
+    t = 16.0  # sqrt(t) = 4: positions scale exactly
+    a = oracle.hot(mu1, mu2, tol=1e-6, max_iter=400000, sigma_update=True,
+                   coord_row=u, coord_col=v)[4]
+    b = oracle.hot(mu1, mu2, tol=1e-6, max_iter=400000, sigma_update=True,
+                   coord_row=4 * u, coord_col=4 * v)[4]
+    assert a["converged"] == 1 and b["converged"] == 1 and a["restarts"] >= 2
+    assert a["iters"] == b["iters"] and a["restarts"] == b["restarts"]
+    assert abs(b["sigma"] * t - a["sigma"]) <= 1e-9 * a["sigma"]
+    assert abs(b["primal_obj"] - t * a["primal_obj"]) <= 1e-9 * t * a["primal_obj"]
+
+
+def test_sigma_update_off_is_default(oracle):
+    rng = np.random.default_rng(3)
+    mu1, mu2 = rand_hist(rng, 5, 6), rand_hist(rng, 5, 6)
+    a = oracle.hot(mu1, mu2, tol=1e-6)
+    b = oracle.hot(mu1, mu2, tol=1e-6, sigma_update=False)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    assert a[4] == b[4]
