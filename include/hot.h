@@ -65,6 +65,14 @@ typedef enum {
 #define HOT_FLAG_ABS_KKT 0x8u     /* stop when ||R(w_bar)|| <= tol, R the
                                      residual map stated before Prop.
                                      complexity, instead of eq. kkt_res */
+#define HOT_FLAG_SIGMA_UPDATE 0x10u /* with the restart rule: at every restart
+                                     set sigma <- ||x_bar - X|| / ||A^T (y_bar - Y)||,
+                                     (X, Y) the w_bar of the previous restart
+                                     (0 before the first); the paper leaves
+                                     sigma open (Algorithm 2 only asks
+                                     sigma > 0).  Costs one more state-sized
+                                     buffer and one more stream on check and
+                                     restart passes. */
 
 typedef struct {
   int32_t m, n;            /* grid rows, columns: 1 <= m, n <= 1024 */
@@ -134,19 +142,22 @@ hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
 
 /* Autotuner of the slab-pass launch shape.  For the shapes and precision of
  * probs (histogram values are ignored: uniform histograms are solved),
- * times `iters` fixed iterations under each candidate workgroup size (2^13 ..
+ * times `iters` fixed iterations (slab pass, reduce and solve, in captured
+ * graphs, hipEvents around the run), each pass streaming the state, a (zero)
+ * Halpern anchor and the new state as every pass after the first restart
+ * does, under each candidate workgroup size (2^13 ..
  * 2^17 flow elements per workgroup), row unroll (1, 2) and 16-byte vectors
- * per lane per slab row (2, 4), with hipEvents
- * around every slab pass, and keeps the fastest in ctx for launches of the
+ * per lane per slab row (2, 4), and keeps the fastest in ctx for launches of the
  * same precision, size class (floor(log2) of the total flow elements) and
  * pair-count class (floor(log2) of the number of problems).  cache_path
  * (nullable): the choice is appended as a JSON line keyed by device
  * architecture, precision, size class and pair-count class;
  * hot_autotune_load reads such a file (later lines win, entries of other
  * architectures are ignored).  out (nullable, 5 doubles): chosen
- * elements per workgroup, chosen unroll, its slab seconds per iteration, the
- * built-in rule's, chosen vectors per lane.  The chunking changes the summation order of column
- * partial sums, so tuned results can differ from untuned ones by rounding. */
+ * elements per workgroup, chosen unroll, its seconds per iteration, the
+ * built-in rule's, chosen vectors per lane.  The chunking changes the
+ * summation order of column partial sums, so tuned results can differ from
+ * untuned ones by rounding. */
 hot_status hot_autotune(hot_ctx *ctx, const hot_problem *probs, int32_t count,
                         int32_t iters, const char *cache_path, double *out);
 hot_status hot_autotune_load(hot_ctx *ctx, const char *cache_path);

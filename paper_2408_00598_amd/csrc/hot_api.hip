@@ -93,11 +93,16 @@ Tuning default_tuning() {
   t.vec_per_lane = 4;
   t.nt_store = 1;
   t.pingpong = 1;
+  t.sep_anchor = 0;
   return t;
 }
 
-size_t Layout::bytes() const {
-  return (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
+size_t Layout::bytes(uint32_t flags) const {
+  // sigma re-balancing keeps x_bar and (alpha, beta) of the last restart
+  const size_t su = (flags & HOT_FLAG_SIGMA_UPDATE)
+                        ? (size_t)state_elems * elem_size + (size_t)tab_off * 8 + 512
+                        : 0;
+  return su + (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
          (size_t)cp_len * 8 * 2 + (size_t)items.size() * (kKI * 8 + sizeof(SlabItem)) +
          (size_t)arr_len * 8 + (size_t)vec_len * 8 + geo.size() * sizeof(PairGeo) +
          (blocks.size() + sblocks.size()) * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 + 4096;
@@ -460,13 +465,41 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
       return HOT_E_INVALID;
     }
   }
-  if (graph_exec && graph_coord != coord) {  // captured with the other slab kernel
+  // sigma re-balancing needs x_bar and y_bar of the last restart
+  int su = 0;
+  for (size_t p = 0; p < np; ++p)
+    if ((probs[p].flags & HOT_FLAG_SIGMA_UPDATE) && (probs[p].flags & HOT_FLAG_RESTART) &&
+        !(probs[p].flags & (HOT_FLAG_FIXED_ITERS | HOT_FLAG_ADMM)))
+      su = 1;
+  if (su && !sbx) {
+    const size_t xb = std::max<size_t>((size_t)lay.state_elems * lay.elem_size, 256);
+    const size_t yb = std::max<size_t>((size_t)lay.tab_off * 8, 256);
+    void* xbuf = nullptr;
+    void* ybuf = nullptr;
+    const bool okx = hipMalloc(&xbuf, xb) == hipSuccess;
+    const bool oky = okx && hipMalloc(&ybuf, yb) == hipSuccess;
+    if (!oky) {
+      (void)hipGetLastError();
+      if (okx) (void)hipFree(xbuf);
+      ctx->err = "hipMalloc failed (sigma re-balancing buffers)";
+      return HOT_E_NOMEM;
+    }
+    sbx = xbuf;
+    abY = (double*)ybuf;
+    allocs.push_back(sbx);
+    allocs.push_back(abY);
+  }
+  const int variant = coord | (su << 1);
+  if (graph_exec && graph_variant != variant) {  // captured with other slab kernels
     (void)hipGraphExecDestroy(graph_exec);
     (void)hipGraphDestroy(graph);
     graph_exec = nullptr;
     graph = nullptr;
   }
   args.coord = coord;
+  args.su = su;
+  args.sbx = su ? sbx : nullptr;
+  args.abY = su ? abY : nullptr;
   HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), np * sizeof(PairGeo), hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(items_d, lay.items.data(), lay.items.size() * sizeof(SlabItem),
                        hipMemcpyHostToDevice, st));
@@ -493,8 +526,13 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     c.max_iter = pr.max_iter;
     c.T = pr.check_every;
     c.flags = (int32_t)pr.flags;
+    // sigma re-balancing acts at restarts only
+    if (!(pr.flags & HOT_FLAG_RESTART) || (pr.flags & (HOT_FLAG_FIXED_ITERS | HOT_FLAG_ADMM)))
+      c.flags &= ~(int32_t)HOT_FLAG_SIGMA_UPDATE;
     if (ctx->tune.pingpong) c.flags |= 0x100;
+    if (ctx->tune.sep_anchor && (pr.flags & HOT_FLAG_FIXED_ITERS)) c.flags |= 0x200;
     c.relax = (pr.flags & HOT_FLAG_ADMM) ? (pr.relax > 0 ? pr.relax : 1.7) : 0.0;
+    c.sig_old = c.sigma;
     c0[np + p] = c;
     c0[np + p].mode = MODE_IDLE;
   }
@@ -506,11 +544,17 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   }
   HIPCK(hipGetLastError());
   HIPCK(hipMemsetAsync(sb[0], 0, (size_t)lay.state_elems * lay.elem_size, st));
+  if (ctx->tune.sep_anchor)
+    HIPCK(hipMemsetAsync(sb[2], 0, (size_t)lay.state_elems * lay.elem_size, st));
   for (int q = 0; q < 2; ++q) {
     HIPCK(hipMemsetAsync(rowsum[q], 0, lay.rs_len * 8, st));
     HIPCK(hipMemsetAsync(colpart[q], 0, lay.cp_len * 8, st));
   }
   HIPCK(hipMemsetAsync(ab, 0, lay.ab_len * 8, st));
+  if (args.su) {  // X = 0, Y = 0 before the first restart (the initial point)
+    HIPCK(hipMemsetAsync(sbx, 0, (size_t)lay.state_elems * lay.elem_size, st));
+    HIPCK(hipMemsetAsync(abY, 0, (size_t)lay.tab_off * 8, st));
+  }
   HIPCK(hipMemcpyAsync(ab + lay.tab_off, tab_host.data(), (size_t)lay.tab_len * 8,
                        hipMemcpyHostToDevice, st));
   HIPCK(hipMemsetAsync(kitem, 0, lay.items.size() * kKI * 8, st));
@@ -537,7 +581,7 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
       return HOT_E_DEVICE;
     }
     HIPCK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
-    graph_coord = args.coord;
+    graph_variant = args.coord | (args.su << 1);
   }
   hipEvent_t ev[2];
   HIPCK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -645,7 +689,7 @@ hot_status Workspace::ensure_graph(hot_ctx* ctx, hipStream_t st) {
     return HOT_E_DEVICE;
   }
   HIPCK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
-  graph_coord = args.coord;
+  graph_variant = args.coord | (args.su << 1);
   return HOT_OK;
 }
 
@@ -771,12 +815,11 @@ hot_status hot_ctx_profile_read(hot_ctx* ctx, double* out) {
 }
 
 size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags) {
-  (void)flags;
   Layout lay;
   std::string err;
   if (prec != HOT_FP64 && prec != HOT_FP32_STREAM) return 0;
   if (!build_layout({{m, n}}, prec == HOT_FP32_STREAM, default_tuning(), lay, err)) return 0;
-  return lay.bytes();
+  return lay.bytes(flags);
 }
 
 int64_t hot_plan_capacity(int32_t m, int32_t n) {

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const PairCtl* __restrict__ ctl, const double* __restrict__ rowsum,
     const double* __restrict__ colpart, const double* __restrict__ rowsum_prev,
     const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
-    const double* __restrict__ ab, double* __restrict__ arr, double* __restrict__ vec) {
+    const double* __restrict__ ab, double* __restrict__ abY, double* __restrict__ arr,
+    double* __restrict__ vec) {
   __shared__ double wred[4][kKP];
   __shared__ double strip[4][64];
   const PBlock pbk = blocks[blockIdx.x];
@@ -177,15 +178,44 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   __syncthreads();
   if (threadIdx.x < 3)
     vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
+  const bool su = (cp->flags & 0x10) != 0;
+  // (alpha, beta) of this wave's slab and their stored copy from the last restart
+  const FamGeo& FS = f1 ? F1 : F2;
+  const int LS = f1 ? m : n;
+  const bool has_slab = f1 ? r < n : r < m;
+  const int64_t aoff = FS.aboff + (int64_t)r * 2 * LS;
+  if (mode == MODE_RESTART && su && has_slab) {
+    // sigma re-balancing: keep y_bar of this restart (alpha, beta, their sums)
+    for (int q = lane; q < 2 * LS; q += 64) abY[aoff + q] = ab[aoff + q];
+    if (lane < 2) abY[FS.sumoff + 2 * (int64_t)r + lane] = ab[FS.sumoff + 2 * (int64_t)r + lane];
+  }
   if (mode != MODE_CHECK) return;
 
   // ---- check pass: KKT partials of w_bar^k -------------------------------
-  double part[kKI] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     const int i0 = G.item0 + slot * G.ipb;
     const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
     for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
-      for (int q = 0; q < 6; ++q) part[q] += kitem[(int64_t)it * kKI + q];
+      for (int q = 0; q <= KI_DX; ++q) part[q] += kitem[(int64_t)it * kKI + q];
+  }
+  if (su && has_slab) {
+    // ||A^T (y_bar - Y)||^2 over this slab: A^T y is alpha_p + beta_q on it,
+    // so the sum over the L x L slab is L sum da^2 + L sum db^2 + 2 sum da sum db
+    double a2 = 0.0, b2 = 0.0, sa_ = 0.0, sb_ = 0.0;
+    for (int q = lane; q < LS; q += 64) {
+      const double da = ab[aoff + q] - abY[aoff + q];
+      const double db = ab[aoff + LS + q] - abY[aoff + LS + q];
+      a2 += da * da;
+      b2 += db * db;
+      sa_ += da;
+      sb_ += db;
+    }
+    a2 = wave_sum(a2);
+    b2 = wave_sum(b2);
+    sa_ = wave_sum(sa_);
+    sb_ = wave_sum(sb_);
+    if (lane == 0) part[KP_DY] = (double)LS * (a2 + b2) + 2.0 * sa_ * sb_;
   }
   // primal residual A xbar - b, xbar = sigma (s - g): the sums of s^k are the
   // previous pass's sums; the sums of g over a slab row / column follow from
@@ -234,12 +264,12 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   part[KP_PRIM] = prim;
   part[KP_BY] = by;
   __syncthreads();
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < kNKP; ++q) {
     const double v = wave_sum(part[q]);
     if (lane == 0) wred[wave][q] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 8)
+  if (threadIdx.x < kNKP)
     vec[vec_kpart(G) + (int64_t)slot * kKP + threadIdx.x] = wave4(wred, threadIdx.x);
 }
 
@@ -251,7 +281,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
 // butterfly); every lane returns the totals.
 __device__ inline void reduce_kpart(const PairGeo& G, const double* vec, int lane, double* acc) {
   const double* kp = vec + vec_kpart(G);
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < kNKP; ++q) {
     double v = 0.0;
     for (int b = lane; b < G.nblk; b += 64) v += kp[(int64_t)b * kKP + q];
     acc[q] = wave_sum(v);
@@ -325,6 +355,14 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
           nx.it = c.it + 1;
           nx.restarts = c.restarts + 1;
           nx.k = 0;
+          nx.sig_old = c.sigma;
+          if (c.flags & 0x10) {
+            // sigma re-balancing: ||x_bar - X|| / ||A^T (y_bar - Y)|| over the
+            // epoch that ends here; the restart pass writes x_bar / sigma_new
+            // + z_bar, and the reduce of that pass already uses sigma_new
+            const double dx = sqrt(acc[KP_DX]), dy = sqrt(acc[KP_DY]);
+            if (dx > 0.0 && dy > 0.0 && isfinite(dx / dy)) nx.sigma = dx / dy;
+          }
           return;  // src keeps s^k for the restart pass
         }
         nx.k = c.k + 1;
@@ -349,6 +387,9 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
   const bool pingpong = (c.flags & 0x100) != 0;  // never update the state in place
   nx.dst = (pingpong || nx.mode == MODE_CHECK || nx.src == 2) ? (nx.src == 0 ? 1 : 0) : nx.src;
   if (admm) nx.anc = nx.src;
+  // timing runs of the autotuner (fixed iterations only): the anchor is a
+  // zero buffer of its own, so passes stream three vectors as after a restart
+  if (c.flags & 0x200) nx.anc = 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +605,7 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
     PairCtl nx;
     if (!FROM_R) {
       const PairCtl c = ctl[pbk.pair];
-      double acc[8];
+      double acc[kNKP];
       if (c.mode == MODE_CHECK) reduce_kpart(G, vec, threadIdx.x, acc);
       decide(G, c, acc, nx, solve);
     }
@@ -783,7 +824,7 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
-                     a.colpart[1 - par], a.kitem, a.ab, a.arr, a.vec);
+                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec);
   hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
                      a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
 }
@@ -793,7 +834,7 @@ void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
   launch_slab_pass(a, par, st);
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
-                     a.colpart[1 - par], a.kitem, a.ab, a.arr, a.vec);
+                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec);
   hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
                      a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
 }

@@ -25,6 +25,8 @@ struct Tuning {
   int vec_per_lane;     // target 16-byte vectors per lane per slab row (2 or 4)
   int nt_store;         // non-temporal stores of the new state
   int pingpong;         // never update the state in place (read one buffer, write the other)
+  int sep_anchor;       // autotuner runs: stream a zero anchor from its own buffer, as
+                        // every pass after the first restart does
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
@@ -69,6 +71,9 @@ struct LaunchArgs {
   int slab_grid = 1;  // workgroups of a slab-pass launch (<= nitems)
   int nt_store = 0;   // non-temporal stores of the new state
   int coord = 0;      // some pair has non-uniform bins: slab passes read positions
+  int su = 0;         // some pair re-balances sigma at restarts
+  void* sbx = nullptr;      // x_bar of the last restart (sigma re-balancing), else null
+  double* abY = nullptr;    // alpha / beta of the last restart (sigma re-balancing)
   unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes
 };
 
@@ -82,7 +87,7 @@ struct Layout {
   int64_t state_elems = 0, ab_len = 0, rs_len = 0, cp_len = 0, arr_len = 0, vec_len = 0;
   int64_t tab_off = 0, tab_len = 0;  // cost tables of every family, inside ab
   int maxvpl = 1;
-  size_t bytes() const;
+  size_t bytes(uint32_t flags = 0) const;  // device bytes; flags: HOT_FLAG_* of the problems
 };
 
 bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
@@ -114,7 +119,9 @@ struct Workspace {
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long* bytes_ctr = nullptr;
   std::vector<double> tab_host;  // cost tables uploaded by setup
-  int graph_coord = 0;           // slab kernel variant the graph was captured with
+  int graph_variant = 0;         // slab kernel variant the graph was captured with
+  void* sbx = nullptr;           // sigma re-balancing buffers, allocated on first use
+  double* abY = nullptr;
   // profiling (events around every slab pass; direct launches)
   bool profile = false;
   double prof_seconds = 0.0;

@@ -85,7 +85,7 @@ static size_t footprint_of(const hot_problem& p, const Tuning& tune) {
   Layout lay;
   std::string err;
   if (!build_layout({{p.m, p.n}}, p.prec == HOT_FP32_STREAM, tune, lay, err)) return 0;
-  return lay.bytes();
+  return lay.bytes(p.flags);
 }
 
 static void server_loop(hot_server* S) {

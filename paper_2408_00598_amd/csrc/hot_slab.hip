@@ -46,17 +46,25 @@ enum { ANC_ZERO = 0, ANC_SAME = 1, ANC_SEP = 2 };
 struct SlabCtx {
   int L, P, r0, r1, lrs, vpl, lin, slot, wave, lane;
   double lam, oml, sigma;
+  double sig_old, ratio;  // sigma re-balancing at a restart: x_bar's sigma, old/new
 };
 
-template <typename T, int MAXVPL, int MODE, int ANC, int U, int C>
+// SU = 1 (check and restart passes of a problem with sigma re-balancing):
+// check passes also read x_bar of the last restart (xr) and accumulate
+// ||x_bar - X||^2; restart passes write x_bar to xr and the new state
+// x_bar / sigma_new + z_bar = (sigma_old / sigma_new)(s - g) + max(0, 2g - s).
+template <typename T, int MAXVPL, int MODE, int ANC, int U, int C, int SU>
 __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
                                  T* __restrict__ dst, const T* __restrict__ anc,
+                                 T* __restrict__ xr,
                                  const double* __restrict__ alpha, const double* __restrict__ bl,
                                  const double* __restrict__ lx,
                                  double (&colacc)[MAXVPL][VecT<T>::W], double* __restrict__ rowsum,
-                                 double (&kk)[6]) {
+                                 double (&kk)[7]) {
   constexpr int W = VecT<T>::W;
   typedef typename VecT<T>::type VT;
+  constexpr bool RDX = SU && MODE == MODE_CHECK;    // read X
+  constexpr bool WRX = SU && MODE == MODE_RESTART;  // write X
   const int LR = 1 << x.lrs, rpw = 64 >> x.lrs;
   const int L = x.L, P = x.P;
   constexpr int UR = U & 3;
@@ -64,6 +72,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
     int prow[UR];
     bool rvv[UR];
     VT xs[UR][MAXVPL], xa[UR][MAXVPL];
+    VT xq[RDX ? UR : 1][RDX ? MAXVPL : 1];
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
       prow[u] = pb + u * 4 * rpw + x.slot;
@@ -74,6 +83,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
         if (v < x.vpl && rvv[u] && q0 < L) {
           xs[u][v] = *reinterpret_cast<const VT*>(src + (int64_t)prow[u] * P + q0);
           if (ANC == ANC_SEP) xa[u][v] = *reinterpret_cast<const VT*>(anc + (int64_t)prow[u] * P + q0);
+          if constexpr (RDX) xq[u][v] = *reinterpret_cast<const VT*>(xr + (int64_t)prow[u] * P + q0);
         }
       }
     }
@@ -88,7 +98,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
       for (int v = 0; v < MAXVPL; ++v) {
         const int q0 = (x.lin + (v << x.lrs)) * W;
         if (v < x.vpl && rv && q0 < L) {
-          VT out;
+          VT out, outx;
           const double d0 = (double)(p - q0);
 #pragma unroll
           for (int e = 0; e < W; ++e) {
@@ -98,7 +108,13 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
             const double g = d * d - (ap + bl[q0 + e]);
             double o;
             if (MODE == MODE_RESTART) {
-              o = fmax(s - g, g);
+              if constexpr (WRX) {
+                const double dd = s - g;
+                o = x.ratio * dd + fmax(0.0, 2.0 * g - s);
+                vset(outx, e, ok ? (T)(x.sig_old * dd) : (T)0);
+              } else {
+                o = fmax(s - g, g);
+              }
             } else {
               const double sh = fabs(s - 2.0 * g);
               if (ANC == ANC_ZERO) o = x.oml * sh;
@@ -116,6 +132,10 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
                 kk[KI_ZZ] += ok ? zb * zb : 0.0;
                 kk[KI_CX] += ok ? d * d * xb : 0.0;
                 kk[KI_FP] += ok ? fr * fr : 0.0;
+                if constexpr (RDX) {
+                  const double dxe = xb - (double)vget(xq[u][v], e);
+                  kk[KI_DX] += ok ? dxe * dxe : 0.0;
+                }
               }
             }
             const T st = ok ? (T)o : (T)0;
@@ -130,6 +150,7 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
                 reinterpret_cast<typename VecT<T>::native*>(dst + (int64_t)p * P + q0));
           else
             *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
+          if constexpr (WRX) *reinterpret_cast<VT*>(xr + (int64_t)p * P + q0) = outx;
         }
       }
       rowacc = group_sum(rowacc, LR);
@@ -141,11 +162,12 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
 // HEAVY = 0: plain update passes; HEAVY = 1: check and restart passes.  Both
 // kernels are launched every iteration; a workgroup whose pair is in the
 // other kind of pass exits at once.
-template <typename T, int MAXVPL, int HEAVY, int U, int C>
+template <typename T, int MAXVPL, int HEAVY, int U, int C, int SU>
 __device__ inline void slab_item(
     int item, const SlabItem* __restrict__ items, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
-    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
+    T* __restrict__ sb2, T* __restrict__ sbx, const double* __restrict__ ab,
+    double* __restrict__ rowsum,
     double* __restrict__ colpart, double* __restrict__ kitem,
     unsigned long long* __restrict__ bytes_ctr, double* lds_col, double* lds_beta, double* lds_x,
     double* red) {
@@ -173,6 +195,10 @@ __device__ inline void slab_item(
   x.lam = cp->lam;
   x.oml = 1.0 - cp->lam;
   x.sigma = cp->sigma;
+  x.sig_old = cp->sig_old;
+  x.ratio = cp->sig_old / cp->sigma;
+  // (SU kernels only) this problem re-balances sigma at restarts
+  const bool su = SU && HEAVY && (cp->flags & 0x10) != 0;
   const int L = F.L;
   const int64_t soff = F.soff + (int64_t)itm.slab * L * F.P;
   const int src_i = cp->src, anc_i = cp->anc;
@@ -182,6 +208,7 @@ __device__ inline void slab_item(
   const int anc_kind =
       (mode == MODE_RESTART || anc_i < 0) ? ANC_ZERO : (anc_i == src_i ? ANC_SAME : ANC_SEP);
   const T* anc = anc_kind == ANC_SEP ? pick<T>(sb0, sb1, sb2, anc_i) + soff : src;
+  T* xr = su ? sbx + soff : nullptr;
   const double* alpha = ab + F.aboff + (int64_t)itm.slab * 2 * L;
   const double* beta = alpha + L;
   double* rs = rowsum + F.rsoff + (int64_t)itm.slab * L;
@@ -200,24 +227,40 @@ __device__ inline void slab_item(
   for (int v = 0; v < MAXVPL; ++v)
 #pragma unroll
     for (int e = 0; e < W; ++e) colacc[v][e] = 0.0;
-  double kk[6] = {0, 0, 0, 0, 0, 0};
+  double kk[7] = {0, 0, 0, 0, 0, 0, 0};
+#define HOT_ROWS(MODE_, ANC_, SU_)                                                        \
+  slab_rows<T, MAXVPL, MODE_, ANC_, U, C, SU_>(x, src, dst, anc, xr, alpha, lds_beta, lds_x, \
+                                               colacc, rs, kk)
   if (!HEAVY) {
-    if (anc_kind == ANC_ZERO)
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else if (anc_kind == ANC_SAME)
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SAME, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else
-      slab_rows<T, MAXVPL, MODE_NORMAL, ANC_SEP, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
+    if (anc_kind == ANC_ZERO) HOT_ROWS(MODE_NORMAL, ANC_ZERO, 0);
+    else if (anc_kind == ANC_SAME) HOT_ROWS(MODE_NORMAL, ANC_SAME, 0);
+    else HOT_ROWS(MODE_NORMAL, ANC_SEP, 0);
   } else if (mode == MODE_CHECK) {
-    if (anc_kind == ANC_ZERO)
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else if (anc_kind == ANC_SAME)
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SAME, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
-    else
-      slab_rows<T, MAXVPL, MODE_CHECK, ANC_SEP, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
+    bool done = false;
+    if constexpr (SU) {
+      if (su) {
+        if (anc_kind == ANC_ZERO) HOT_ROWS(MODE_CHECK, ANC_ZERO, 1);
+        else if (anc_kind == ANC_SAME) HOT_ROWS(MODE_CHECK, ANC_SAME, 1);
+        else HOT_ROWS(MODE_CHECK, ANC_SEP, 1);
+        done = true;
+      }
+    }
+    if (!done) {
+      if (anc_kind == ANC_ZERO) HOT_ROWS(MODE_CHECK, ANC_ZERO, 0);
+      else if (anc_kind == ANC_SAME) HOT_ROWS(MODE_CHECK, ANC_SAME, 0);
+      else HOT_ROWS(MODE_CHECK, ANC_SEP, 0);
+    }
   } else {
-    slab_rows<T, MAXVPL, MODE_RESTART, ANC_ZERO, U, C>(x, src, dst, anc, alpha, lds_beta, lds_x, colacc, rs, kk);
+    bool done = false;
+    if constexpr (SU) {
+      if (su) {
+        HOT_ROWS(MODE_RESTART, ANC_ZERO, 1);
+        done = true;
+      }
+    }
+    if (!done) HOT_ROWS(MODE_RESTART, ANC_ZERO, 0);
   }
+#undef HOT_ROWS
 
   // column partials: fold the row slots of the wave, then the four waves
   const int LR = 1 << x.lrs;
@@ -244,25 +287,29 @@ __device__ inline void slab_item(
     cpo[q] = (lds_col[q] + lds_col[S + q]) + (lds_col[2 * S + q] + lds_col[3 * S + q]);
   if (threadIdx.x == 0 && bytes_ctr) {
     // algorithmic stream traffic of this item: read s (and the anchor when it
-    // is a separate buffer), write the new state
-    const int streams = anc_kind == ANC_SEP ? 3 : 2;
+    // is a separate buffer), write the new state; with sigma re-balancing,
+    // read (check) or write (restart) x_bar of the last restart
+    const int streams = (anc_kind == ANC_SEP ? 3 : 2) + (su ? 1 : 0);
     atomicAdd(bytes_ctr, (unsigned long long)(x.r1 - x.r0) * L * sizeof(T) * streams);
   }
   if (HEAVY && mode == MODE_CHECK) {
     double* ko = kitem + (int64_t)item * kKI;
-    double r[6];
-    for (int q = 0; q < 6; ++q) r[q] = block_sum(kk[q], red);
+    const int nq = su ? 7 : 6;
+    double r[7];
+    for (int q = 0; q < nq; ++q) r[q] = block_sum(kk[q], red);
     if (threadIdx.x == 0)
-      for (int q = 0; q < 6; ++q) ko[q] = r[q];
+      for (int q = 0; q < nq; ++q) ko[q] = r[q];
   }
 }
 
-// One workgroup per item.
-template <typename T, int MAXVPL, int HEAVY, int U, int C>
+// One workgroup per item.  SU = 1 (check / restart kernel only): some problem
+// of the launch re-balances sigma at restarts.
+template <typename T, int MAXVPL, int HEAVY, int U, int C, int SU>
 __global__ __launch_bounds__(kWG) void k_slab_pass(
     const SlabItem* __restrict__ items, int nitems, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
-    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
+    T* __restrict__ sb2, T* __restrict__ sbx, const double* __restrict__ ab,
+    double* __restrict__ rowsum,
     double* __restrict__ colpart, double* __restrict__ kitem,
     unsigned long long* __restrict__ bytes_ctr) {
   constexpr int W = VecT<T>::W;
@@ -272,15 +319,24 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
   __shared__ double lds_x[C ? S : 1];
   __shared__ double red[4];
   if ((int)blockIdx.x < nitems)
-    slab_item<T, MAXVPL, HEAVY, U, C>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, ab, rowsum,
+    slab_item<T, MAXVPL, HEAVY, U, C, SU>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, sbx, ab, rowsum,
                                       colpart, kitem, bytes_ctr, lds_col, lds_beta, lds_x, red);
 }
 
 template <typename T, int V, int U, int C>
 static void launch_lean(const LaunchArgs& a, int par, hipStream_t st) {
-  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U, C>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                     a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
-                     a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U, C, 0>), dim3(a.slab_grid), dim3(kWG), 0, st,
+                     a.items, a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1],
+                     (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem,
+                     a.bytes_ctr);
+}
+
+template <typename T, int V, int C, int SU>
+static void launch_heavy(const LaunchArgs& a, int par, hipStream_t st) {
+  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, C, SU>), dim3(a.slab_grid), dim3(kWG), 0, st,
+                     a.items, a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1],
+                     (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem,
+                     a.bytes_ctr);
 }
 
 template <typename T, int V>
@@ -288,9 +344,8 @@ static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
   if (a.coord) {  // non-uniform bins: positions from LDS, one row per wave step
     if (a.nt_store) launch_lean<T, V, 5, 1>(a, par, st);
     else launch_lean<T, V, 1, 1>(a, par, st);
-    hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, 1>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                       a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
-                       a.rowsum[par], a.colpart[par], a.kitem, a.bytes_ctr);
+    if (a.su) launch_heavy<T, V, 1, 1>(a, par, st);
+    else launch_heavy<T, V, 1, 0>(a, par, st);
     return;
   }
   const int u = (a.unroll >= 2 ? 2 : 1) | (a.nt_store ? 4 : 0);
@@ -300,10 +355,8 @@ static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
     case 5: launch_lean<T, V, 5, 0>(a, par, st); break;
     default: launch_lean<T, V, 6, 0>(a, par, st); break;
   }
-  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, 0>), dim3(a.slab_grid), dim3(kWG), 0, st, a.items,
-                     a.nitems, a.geo,
-                     a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab, a.rowsum[par],
-                     a.colpart[par], a.kitem, a.bytes_ctr);
+  if (a.su) launch_heavy<T, V, 0, 1>(a, par, st);
+  else launch_heavy<T, V, 0, 0>(a, par, st);
 }
 
 template <typename T>

@@ -18,6 +18,7 @@ HOT_OK, HOT_E_INVALID, HOT_E_NOMEM, HOT_E_DEVICE, HOT_E_NOT_CONVERGED = 0, 1, 2,
 HOT_E_BUSY, HOT_E_CANCELLED, HOT_E_NUMERIC = 5, 6, 7
 HOT_FP64, HOT_FP32_STREAM = 0, 1
 HOT_FLAG_RESTART, HOT_FLAG_FIXED_ITERS, HOT_FLAG_ADMM, HOT_FLAG_ABS_KKT = 0x1, 0x2, 0x4, 0x8
+HOT_FLAG_SIGMA_UPDATE = 0x10
 
 EXPORTED = [
     "hot_ctx_create", "hot_ctx_destroy", "hot_ctx_last_error", "hot_status_string",
@@ -230,7 +231,7 @@ class Context:
         if st != HOT_OK:
             raise HotError(st, self.last_error())
         return {"item_elems": int(out[0]), "unroll": int(out[1]),
-                "slab_us_per_iter": out[2] * 1e6, "default_us_per_iter": out[3] * 1e6,
+                "us_per_iter": out[2] * 1e6, "default_us_per_iter": out[3] * 1e6,
                 "vec_per_lane": int(out[4])}
 
     def autotune_load(self, cache_path):
