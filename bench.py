@@ -97,11 +97,13 @@ def run_serving(args):
             pool[n].append((torch.tensor(a, device=dev), torch.tensor(b, device=dev)))
     torch.cuda.synchronize()
     ctx = hot.Context(0)
+    flags = hot.HOT_FLAG_RESTART | (hot.HOT_FLAG_SIGMA_UPDATE if args.sigma_update else 0)
     # warm the per-shape workspaces and graphs
     srv = hot.Server(ctx, max_slots=args.slots)
     for n in workloads.SERVE_SIDES:
         for prec, tol in ((hot.HOT_FP32_STREAM, 1e-4), (hot.HOT_FP64, 1e-6)):
-            srv.submit(*pool[n][0], -1, tol=tol, prec=prec, max_iter=1000000)
+            # (a few quanta only: this builds the workspaces and graphs)
+            srv.submit(*pool[n][0], -1, tol=tol, prec=prec, max_iter=100, flags=flags)
     srv.drain(600.0)
     srv.poll(1024)
     srv.close()
@@ -116,7 +118,7 @@ def run_serving(args):
                 time.sleep(t - now)
             a, b = pool[n][seed % args.pool]
             prec = hot.HOT_FP32_STREAM if tol >= 1e-4 else hot.HOT_FP64
-            srv.submit(a, b, q, tol=tol, prec=prec, max_iter=1000000)
+            srv.submit(a, b, q, tol=tol, prec=prec, max_iter=1000000, flags=flags)
 
     th = threading.Thread(target=feeder)
     th.start()
@@ -151,7 +153,8 @@ def run_serving(args):
         "data": "synthetic",
         "config": {"workload": f"serving: Poisson {args.rate:g} req/s for {args.duration:g} s, "
                                "n~U{64,96,128,192,256}, 1-5 Gaussian blobs, tol 1e-4 (70%, FP32 "
-                               "streams) / 1e-6 (30%, FP64), continuous batching",
+                               "streams) / 1e-6 (30%, FP64), continuous batching"
+                               + (", sigma re-balanced at restarts" if args.sigma_update else ""),
                    "requests": len(trace), "slots": args.slots},
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
         "offered_rate": args.rate, "completed": len(results),
@@ -240,6 +243,8 @@ def main():
     ap.add_argument("--drain", type=float, default=20.0,
                     help="serving: seconds to keep draining after the last arrival")
     ap.add_argument("--pool", type=int, default=8, help="serving distinct pairs per side")
+    ap.add_argument("--sigma-update", action="store_true",
+                    help="serving: requests re-balance sigma at restarts (HOT_FLAG_SIGMA_UPDATE)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) 5 times, for scaling "
                          "hardware byte counters")
@@ -279,7 +284,7 @@ def main():
         hit = None if args.retune else cached_choice(args.tune_cache, fp32, total, len(pairs))
         if hit is not None and ctx.autotune_load(args.tune_cache):
             tuned = {k: hit[k] for k in ("item_elems", "unroll", "vec_per_lane",
-                                         "slab_us_per_iter", "default_us_per_iter")}
+                                         "us_per_iter", "default_us_per_iter")}
             tuned["source"] = "cache"
         else:
             tuned = ctx.autotune(dpairs, iters=30, prec=prec,
