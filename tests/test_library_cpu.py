@@ -53,3 +53,71 @@ def test_no_gpu_context_fails_cleanly():
     from paper_2408_00598_amd import hot
     with pytest.raises(hot.HotError):
         hot.Context(0)
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a struct of include/hot.h, from gcc."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hot.h"', 'int main(void) {',
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("name", ["Problem", "Result", "ServerConfig"])
+def test_binding_structs_match_header(tmp_path, name):
+    """The ctypes structures of the binding have the header's size and field
+    offsets (compiled with gcc against include/hot.h)."""
+    from paper_2408_00598_amd import hot
+    cls = getattr(hot, name)
+    cname = {"Problem": "hot_problem", "Result": "hot_result",
+             "ServerConfig": "hot_server_config"}[name]
+    fields = [f for f, _ in cls._fields_]
+    got = _c_layout(tmp_path, cname, fields)
+    assert got[0] == C_sizeof(cls), (cname, got[0])
+    for f, off in zip(fields, got[1:]):
+        assert getattr(cls, f).offset == off, (cname, f)
+
+
+def C_sizeof(cls):
+    import ctypes
+    return ctypes.sizeof(cls)
+
+
+def test_binding_flag_constants_match_header():
+    from paper_2408_00598_amd import hot
+    text = open(os.path.join(ROOT, "include", "hot.h")).read()
+    defs = dict(re.findall(r"#define (HOT_FLAG_[A-Z_]+) (0x[0-9a-f]+)u", text))
+    assert set(defs) == {"HOT_FLAG_RESTART", "HOT_FLAG_FIXED_ITERS", "HOT_FLAG_ADMM",
+                         "HOT_FLAG_ABS_KKT", "HOT_FLAG_SIGMA_UPDATE"}
+    for k, v in defs.items():
+        assert getattr(hot, k) == int(v, 16), k
+
+
+@pytest.mark.parametrize("name,cname", [("Params", "or_params"), ("Result", "or_result")])
+def test_oracle_binding_structs_match_header(tmp_path, name, cname):
+    """Same check for the oracle's ctypes wrapper against oracle/hot_oracle.h."""
+    import subprocess
+    from oracle import oracle as O
+    cls = getattr(O, name)
+    fields = [f for f, _ in cls._fields_]
+    src = tmp_path / "ol.c"
+    body = [f'  printf("%zu\\n", sizeof({cname}));']
+    body += [f'  printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hot_oracle.h"\n'
+                   'int main(void) {\n' + "\n".join(body) + '\n  return 0;\n}\n')
+    exe = tmp_path / "ol"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "oracle"), str(src), "-o",
+                    str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got[0] == C_sizeof(cls)
+    for f, off in zip(fields, got[1:]):
+        assert getattr(cls, f).offset == off, (cname, f)
