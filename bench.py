@@ -283,8 +283,8 @@ def main():
         total = sum(a.shape[0] ** 2 * a.shape[1] + a.shape[0] * a.shape[1] ** 2 for a, _ in pairs)
         hit = None if args.retune else cached_choice(args.tune_cache, fp32, total, len(pairs))
         if hit is not None and ctx.autotune_load(args.tune_cache):
-            tuned = {k: hit[k] for k in ("item_elems", "unroll", "vec_per_lane",
-                                         "us_per_iter", "default_us_per_iter")}
+            tuned = {k: hit.get(k) for k in ("item_elems", "unroll", "vec_per_lane",
+                                             "us_per_iter", "default_us_per_iter")}
             tuned["source"] = "cache"
         else:
             tuned = ctx.autotune(dpairs, iters=30, prec=prec,

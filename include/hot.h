@@ -134,9 +134,9 @@ const char *hot_status_string(hot_status s);
  * solver's stream.  hot_ctx_profile_read fills out[4] with counters summed
  * over all solves since profiling was last switched:
  *   out[0] slab-pass launches timed, out[1] their total seconds (events),
- *   out[2] algorithmic bytes streamed by slab passes (state read + anchor read
- *          when separate + state write, padding excluded; counted in graph
- *          mode too), out[3] iterations launched. */
+ *   out[2] algorithmic bytes streamed by the timed slab passes (state read +
+ *          anchor read when separate + state write, padding excluded),
+ *   out[3] iterations launched. */
 hot_status hot_ctx_set_profiling(hot_ctx *ctx, int on);
 hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
 
@@ -231,8 +231,8 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
  * iterated on its own stream by its captured graph, so problems admitted at
  * different times run concurrently; iterates stay on the device until the
  * problem stops.  A problem's result equals its hot_solve result.
- * submit: non-blocking; the histograms must stay valid until its result has
- *   been polled.  HOT_E_INVALID for a malformed problem (histogram values are
+ * submit: non-blocking; the histograms (and grid-line positions, if any)
+ *   must stay valid until its result has been polled.  HOT_E_INVALID for a malformed problem (histogram values are
  *   validated at admission and reported in the result status), HOT_E_NOMEM
  *   if its footprint alone exceeds the budget.
  * poll: copies up to max finished results (each returned once) with their

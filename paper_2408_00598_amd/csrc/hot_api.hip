@@ -94,6 +94,7 @@ Tuning default_tuning() {
   t.nt_store = 1;
   t.pingpong = 1;
   t.sep_anchor = 0;
+  t.small_side = 64;
   return t;
 }
 
@@ -104,6 +105,7 @@ size_t Layout::bytes(uint32_t flags) const {
                         : 0;
   return su + (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
          (size_t)cp_len * 8 * 2 + (size_t)items.size() * (kKI * 8 + sizeof(SlabItem)) +
+         sitems.size() * sizeof(SmallItem) +
          (size_t)arr_len * 8 + (size_t)vec_len * 8 + geo.size() * sizeof(PairGeo) +
          (blocks.size() + sblocks.size()) * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 + 4096;
 }
@@ -152,9 +154,10 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       F.vpl = vpl;
       maxvpl = std::max(maxvpl, vpl);
       const int step = 8 * (64 / LR);  // rows one workgroup covers per (two-row) step
+      const bool small = F.L <= tune.small_side;  // whole slab per wave
       int rows = (int)std::max<int64_t>(1, item_elems / F.P);
       rows = (int)round_up(rows, step);
-      if (rows >= F.L) rows = F.L;
+      if (rows >= F.L || small) rows = F.L;
       F.rpc = rows;
       F.nchunk = (F.L + rows - 1) / rows;
       soff = round_up(soff, 64);
@@ -171,7 +174,12 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       F.cpoff = cpoff;
       cpoff += (int64_t)F.nslab * F.nchunk * F.L;
       for (int s = 0; s < F.nslab; ++s)
-        for (int c = 0; c < F.nchunk; ++c) lay.items.push_back(SlabItem{(int32_t)p, fam, s, c});
+        for (int c = 0; c < F.nchunk; ++c)
+          lay.items.push_back(SlabItem{(int32_t)p, fam, s, c, (int32_t)lay.items.size(),
+                                       small ? 1 : 0, 0, 0});
+      if (small)
+        for (int s = 0; s < F.nslab; s += 4)
+          lay.sitems.push_back(SmallItem{(int32_t)p, fam, s, std::min(4, F.nslab - s)});
     }
     g.nitem = (int32_t)lay.items.size() - g.item0;
     g.nb1 = (n + 3) / 4;                // reduce row blocks: rows j = 4b..4b+3 of F1,
@@ -197,6 +205,13 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
     g.norm_c = std::sqrt((double)n * slab_cost_sq(m) + (double)m * slab_cost_sq(n));
     lay.geo.push_back(g);
   }
+  // launch order: items of the block plain-update pass first (the check /
+  // restart kernel runs over all of them); kslot keeps each pair's KKT
+  // partial slots contiguous
+  std::stable_partition(lay.items.begin(), lay.items.end(),
+                        [](const SlabItem& it) { return it.small == 0; });
+  lay.nbig = 0;
+  for (const SlabItem& it : lay.items) lay.nbig += it.small == 0;
   lay.state_elems = round_up(std::max<int64_t>(soff, 64), 64);
   for (PairGeo& g : lay.geo)
     for (int fam = 0; fam < 2; ++fam) g.f[fam].xoff += aboff;
@@ -283,6 +298,8 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   if ((st = A((void**)&arr, lay.arr_len * 8)) != HOT_OK) return st;
   if ((st = A((void**)&vec, lay.vec_len * 8)) != HOT_OK) return st;
   if ((st = A((void**)&items_d, lay.items.size() * sizeof(SlabItem))) != HOT_OK) return st;
+  if ((st = A((void**)&sitems_d, std::max<size_t>(lay.sitems.size(), 1) * sizeof(SmallItem))) != HOT_OK)
+    return st;
   if ((st = A((void**)&blocks_d, lay.blocks.size() * sizeof(PBlock))) != HOT_OK) return st;
   if ((st = A((void**)&sblocks_d, lay.sblocks.size() * sizeof(PBlock))) != HOT_OK) return st;
   if ((st = A((void**)&geo_d, lay.geo.size() * sizeof(PairGeo))) != HOT_OK) return st;
@@ -297,6 +314,9 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   }
   args.items = items_d;
   args.nitems = (int)lay.items.size();
+  args.nbig = (int)lay.nbig;
+  args.sitems = sitems_d;
+  args.nsitems = (int)lay.sitems.size();
   args.blocks = blocks_d;
   args.nblocks = (int)lay.blocks.size();
   args.sblocks = sblocks_d;
@@ -503,6 +523,9 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), np * sizeof(PairGeo), hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(items_d, lay.items.data(), lay.items.size() * sizeof(SlabItem),
                        hipMemcpyHostToDevice, st));
+  if (!lay.sitems.empty())
+    HIPCK(hipMemcpyAsync(sitems_d, lay.sitems.data(), lay.sitems.size() * sizeof(SmallItem),
+                         hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(blocks_d, lay.blocks.data(), lay.blocks.size() * sizeof(PBlock),
                        hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(sblocks_d, lay.sblocks.data(), lay.sblocks.size() * sizeof(PBlock),
@@ -780,6 +803,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.item_elems = std::max<int64_t>(1024, std::atoll(e));
   e = std::getenv("HOT_MIN_ITEMS");
   if (e) c->tune.min_items = std::max<int64_t>(1, std::atoll(e));
+  e = std::getenv("HOT_SMALL_SIDE");
+  if (e) c->tune.small_side = std::max(0, std::atoi(e));
   e = std::getenv("HOT_VPL_TARGET");
   if (e) c->tune.vec_per_lane = std::max(1, std::min(8, std::atoi(e)));
   e = std::getenv("HOT_NT_STORE");
@@ -864,8 +889,9 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
       total += (int64_t)probs[p].m * probs[p].m * probs[p].n + (int64_t)probs[p].m * probs[p].n * probs[p].n;
     ws->args.unroll = ctx->tune.unroll_for(total, count, prec == HOT_FP32_STREAM);
   }
-  ws->args.slab_grid = ws->args.nitems;
   ws->args.nt_store = ctx->tune.nt_store;
+  // the algorithmic byte count is kept only when the passes are timed
+  ws->args.bytes_ctr = ws->profile ? ws->bytes_ctr : nullptr;
   if (s != HOT_OK) return s;
   if (hipStreamCreateWithFlags(&ws->stream, hipStreamNonBlocking) != hipSuccess) {
     ctx->err = "stream creation failed";

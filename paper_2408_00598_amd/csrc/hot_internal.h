@@ -124,8 +124,20 @@ __host__ __device__ inline int64_t vec_size(const PairGeo& g) {
          (int64_t)g.nblk * kKP;
 }
 
+// One workgroup of the block slab pass: a row chunk of one slab.  kslot is
+// the item's KKT-partial slot (contiguous per pair, in (fam, slab, chunk)
+// order); small = 1 marks slabs whose plain-update passes run in the
+// wave-per-slab kernel instead (the block kernels still run their check and
+// restart passes).
 struct SlabItem {
   int32_t pair, fam, slab, chunk;
+  int32_t kslot, small, pad0, pad1;
+};
+
+// One workgroup of the wave-per-slab pass: up to four consecutive slabs of
+// one family, one wave each (small slabs, whole slab per wave).
+struct SmallItem {
+  int32_t pair, fam, slab0, nslab;
 };
 
 struct PBlock {

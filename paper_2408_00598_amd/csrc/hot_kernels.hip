@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const double* __restrict__ colpart, const double* __restrict__ rowsum_prev,
     const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
     const double* __restrict__ ab, double* __restrict__ abY, double* __restrict__ arr,
-    double* __restrict__ vec) {
+    double* __restrict__ vec, unsigned long long* __restrict__ bytes_ctr, int elem) {
   __shared__ double wred[4][kKP];
   __shared__ double strip[4][64];
   const PBlock pbk = blocks[blockIdx.x];
@@ -82,6 +82,16 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   const int m = G.m, n = G.n, b = pbk.blk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const FamGeo F1 = G.f[0], F2 = G.f[1];
+  if (bytes_ctr && pbk.kind == 0 && b == 0 && threadIdx.x == 0 && mode != MODE_INIT) {
+    // measurement only: algorithmic bytes of the slab pass this pair just
+    // had -- read the state (and the anchor when it is a buffer of its own),
+    // write the new state; with sigma re-balancing also read (check) or
+    // write (restart) x_bar of the last restart; padding excluded
+    const bool sep = mode != MODE_RESTART && cp->anc >= 0 && cp->anc != cp->src;
+    const bool xr = (cp->flags & 0x10) && (mode == MODE_CHECK || mode == MODE_RESTART);
+    const unsigned long long N = (unsigned long long)m * m * n + (unsigned long long)m * n * n;
+    atomicAdd(bytes_ctr, N * (unsigned long long)elem * (2ull + (sep ? 1 : 0) + (xr ? 1 : 0)));
+  }
   if (pbk.kind == 1 || pbk.kind == 2) {
     // column totals of a row-sum array: lane = column, waves split the rows
     const bool s1 = pbk.kind == 1;
@@ -824,7 +834,8 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
-                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec);
+                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec, a.bytes_ctr,
+                     a.fp32 ? 4 : 8);
   hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
                      a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
 }
@@ -834,7 +845,8 @@ void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
   launch_slab_pass(a, par, st);
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
-                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec);
+                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec, a.bytes_ctr,
+                     a.fp32 ? 4 : 8);
   hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
                      a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
 }

@@ -27,6 +27,8 @@ struct Tuning {
   int pingpong;         // never update the state in place (read one buffer, write the other)
   int sep_anchor;       // autotuner runs: stream a zero anchor from its own buffer, as
                         // every pass after the first restart does
+  int small_side;       // families with slab side <= this run plain-update passes
+                        // wave-per-slab (whole slab per wave, no block barriers)
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
@@ -52,6 +54,9 @@ inline Tuning::Key tune_key(int fp32, int64_t elems, int npairs) {
 struct LaunchArgs {
   const SlabItem* items = nullptr;
   int nitems = 0;
+  int nbig = 0;                       // block items whose plain passes use the block kernel
+  const SmallItem* sitems = nullptr;  // wave-per-slab items
+  int nsitems = 0;
   const PBlock* blocks = nullptr;   // reduce blocks
   int nblocks = 0;
   const PBlock* sblocks = nullptr;  // solve blocks
@@ -68,7 +73,6 @@ struct LaunchArgs {
   int fp32 = 0;
   int maxvpl = 1;
   int unroll = 1;  // rows loaded ahead per wave in the plain update pass
-  int slab_grid = 1;  // workgroups of a slab-pass launch (<= nitems)
   int nt_store = 0;   // non-temporal stores of the new state
   int coord = 0;      // some pair has non-uniform bins: slab passes read positions
   int su = 0;         // some pair re-balances sigma at restarts
@@ -81,7 +85,9 @@ struct Layout {
   int fp32 = 0;
   int elem_size = 8;
   std::vector<PairGeo> geo;
-  std::vector<SlabItem> items;
+  std::vector<SlabItem> items;      // block items; the first nbig are not small
+  int64_t nbig = 0;
+  std::vector<SmallItem> sitems;    // wave-per-slab items
   std::vector<PBlock> blocks;
   std::vector<PBlock> sblocks;
   int64_t state_elems = 0, ab_len = 0, rs_len = 0, cp_len = 0, arr_len = 0, vec_len = 0;
@@ -106,6 +112,7 @@ struct Workspace {
   double* arr = nullptr;
   double* vec = nullptr;
   SlabItem* items_d = nullptr;
+  SmallItem* sitems_d = nullptr;
   PBlock* blocks_d = nullptr;
   PBlock* sblocks_d = nullptr;
   PairGeo* geo_d = nullptr;

@@ -169,8 +169,7 @@ __device__ inline void slab_item(
     T* __restrict__ sb2, T* __restrict__ sbx, const double* __restrict__ ab,
     double* __restrict__ rowsum,
     double* __restrict__ colpart, double* __restrict__ kitem,
-    unsigned long long* __restrict__ bytes_ctr, double* lds_col, double* lds_beta, double* lds_x,
-    double* red) {
+    double* lds_col, double* lds_beta, double* lds_x, double* red) {
   constexpr int W = VecT<T>::W;
   constexpr int S = 64 * MAXVPL * W;
   const SlabItem itm = items[item];
@@ -179,6 +178,7 @@ __device__ inline void slab_item(
   const int mode = cp->mode;
   if (status != ST_RUNNING) return;
   if (HEAVY ? (mode != MODE_CHECK && mode != MODE_RESTART) : (mode != MODE_NORMAL)) return;
+  if (!HEAVY && itm.small) return;  // (not launched: small items follow the first nbig)
   // (uniform per workgroup: every thread reads the same control block)
   const FamGeo F = geo[itm.pair].f[itm.fam];
   SlabCtx x;
@@ -285,15 +285,8 @@ __device__ inline void slab_item(
   double* cpo = colpart + F.cpoff + ((int64_t)itm.slab * F.nchunk + itm.chunk) * L;
   for (int q = threadIdx.x; q < L; q += kWG)
     cpo[q] = (lds_col[q] + lds_col[S + q]) + (lds_col[2 * S + q] + lds_col[3 * S + q]);
-  if (threadIdx.x == 0 && bytes_ctr) {
-    // algorithmic stream traffic of this item: read s (and the anchor when it
-    // is a separate buffer), write the new state; with sigma re-balancing,
-    // read (check) or write (restart) x_bar of the last restart
-    const int streams = (anc_kind == ANC_SEP ? 3 : 2) + (su ? 1 : 0);
-    atomicAdd(bytes_ctr, (unsigned long long)(x.r1 - x.r0) * L * sizeof(T) * streams);
-  }
   if (HEAVY && mode == MODE_CHECK) {
-    double* ko = kitem + (int64_t)item * kKI;
+    double* ko = kitem + (int64_t)itm.kslot * kKI;
     const int nq = su ? 7 : 6;
     double r[7];
     for (int q = 0; q < nq; ++q) r[q] = block_sum(kk[q], red);
@@ -310,8 +303,7 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
     const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
     T* __restrict__ sb2, T* __restrict__ sbx, const double* __restrict__ ab,
     double* __restrict__ rowsum,
-    double* __restrict__ colpart, double* __restrict__ kitem,
-    unsigned long long* __restrict__ bytes_ctr) {
+    double* __restrict__ colpart, double* __restrict__ kitem) {
   constexpr int W = VecT<T>::W;
   constexpr int S = 64 * MAXVPL * W;
   __shared__ double lds_col[4 * S];
@@ -320,23 +312,177 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
   __shared__ double red[4];
   if ((int)blockIdx.x < nitems)
     slab_item<T, MAXVPL, HEAVY, U, C, SU>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, sbx, ab, rowsum,
-                                      colpart, kitem, bytes_ctr, lds_col, lds_beta, lds_x, red);
+                                      colpart, kitem, lds_col, lds_beta, lds_x, red);
+}
+
+// ---------------------------------------------------------------------------
+// Wave-per-slab plain-update pass for small slabs (side <= a tunable, 64 by
+// default).  A block pass over a 32 x 32 slab keeps most of a workgroup idle
+// and pays two barriers and an LDS round trip for 4 KB of state; here each
+// wave owns a whole slab: beta (and the column positions) sit in registers
+// for the lane's fixed columns, rows are streamed in steps of 64 / LR, the row
+// sums use the same DPP tree and the column sums fold the wave's row slots
+// with shuffles, so the kernel has no barrier at all.  The arithmetic per
+// element is the block pass's, term for term.
+// ---------------------------------------------------------------------------
+template <typename T, int MAXVPL, int ANC, int U, int C>
+__device__ inline void slab_wave(const SlabCtx& x, const T* __restrict__ src,
+                                 T* __restrict__ dst, const T* __restrict__ anc,
+                                 const double* __restrict__ alpha,
+                                 const double* __restrict__ beta, const double* __restrict__ X,
+                                 double* __restrict__ rowsum, double* __restrict__ colout) {
+  constexpr int W = VecT<T>::W;
+  typedef typename VecT<T>::type VT;
+  const int LR = 1 << x.lrs, rpw = 64 >> x.lrs;
+  const int L = x.L, P = x.P;
+  constexpr int UR = U & 3;
+  double bq[MAXVPL][W], xq[C ? MAXVPL : 1][C ? W : 1], colacc[MAXVPL][W];
+#pragma unroll
+  for (int v = 0; v < MAXVPL; ++v)
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int q = (x.lin + (v << x.lrs)) * W + e;
+      const bool in = v < x.vpl && q < L;
+      bq[v][e] = in ? beta[q] : 0.0;
+      if constexpr (C) xq[v][e] = in ? X[q] : 0.0;
+      colacc[v][e] = 0.0;
+    }
+  for (int pb = x.slot; pb < L; pb += UR * rpw) {
+    int prow[UR];
+    bool rvv[UR];
+    VT xs[UR][MAXVPL], xa[UR][MAXVPL];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      prow[u] = pb + u * rpw;
+      rvv[u] = prow[u] < L;
+#pragma unroll
+      for (int v = 0; v < MAXVPL; ++v) {
+        const int q0 = (x.lin + (v << x.lrs)) * W;
+        if (v < x.vpl && rvv[u] && q0 < L) {
+          xs[u][v] = *reinterpret_cast<const VT*>(src + (int64_t)prow[u] * P + q0);
+          if (ANC == ANC_SEP) xa[u][v] = *reinterpret_cast<const VT*>(anc + (int64_t)prow[u] * P + q0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const int p = prow[u];
+      const bool rv = rvv[u];
+      const double ap = rv ? alpha[p] : 0.0;
+      const double xp = (C && rv) ? X[p] : 0.0;
+      double rowacc = 0.0;
+#pragma unroll
+      for (int v = 0; v < MAXVPL; ++v) {
+        const int q0 = (x.lin + (v << x.lrs)) * W;
+        if (v < x.vpl && rv && q0 < L) {
+          VT out;
+          const double d0 = (double)(p - q0);
+#pragma unroll
+          for (int e = 0; e < W; ++e) {
+            const bool ok = (q0 + e) < L;
+            const double s = (double)vget(xs[u][v], e);
+            double d;
+            if constexpr (C) d = xp - xq[v][e];
+            else d = d0 - (double)e;
+            const double g = d * d - (ap + bq[v][e]);
+            const double sh = fabs(s - 2.0 * g);
+            double o;
+            if (ANC == ANC_ZERO) o = x.oml * sh;
+            else if (ANC == ANC_SAME) o = x.lam * s + x.oml * sh;
+            else o = x.lam * (double)vget(xa[u][v], e) + x.oml * sh;
+            const T st = ok ? (T)o : (T)0;
+            const double sd = (double)st;
+            rowacc += sd;
+            colacc[v][e] += sd;
+            vset(out, e, st);
+          }
+          if (U & 4)
+            __builtin_nontemporal_store(
+                __builtin_bit_cast(typename VecT<T>::native, out),
+                reinterpret_cast<typename VecT<T>::native*>(dst + (int64_t)p * P + q0));
+          else
+            *reinterpret_cast<VT*>(dst + (int64_t)p * P + q0) = out;
+        }
+      }
+      rowacc = group_sum(rowacc, LR);
+      if (rv && x.lin == LR - 1) rowsum[p] = rowacc;
+    }
+  }
+  // column sums: fold the wave's row slots
+#pragma unroll
+  for (int v = 0; v < MAXVPL; ++v)
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      double t = colacc[v][e];
+      for (int off = LR; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+      const int q = (x.lin + (v << x.lrs)) * W + e;
+      if (x.slot == 0 && v < x.vpl && q < L) colout[q] = t;
+    }
+}
+
+template <typename T, int MAXVPL, int U, int C>
+__global__ __launch_bounds__(kWG) void k_slab_small(
+    const SmallItem* __restrict__ items, const PairGeo* __restrict__ geo,
+    const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
+    T* __restrict__ sb2, const double* __restrict__ ab, double* __restrict__ rowsum,
+    double* __restrict__ colpart) {
+  const SmallItem itm = items[blockIdx.x];
+  const int wave = threadIdx.x >> 6;
+  if (wave >= itm.nslab) return;
+  const PairCtl* cp = ctl + itm.pair;
+  if (cp->status != ST_RUNNING || cp->mode != MODE_NORMAL) return;
+  const FamGeo F = geo[itm.pair].f[itm.fam];
+  const int slab = itm.slab0 + wave;
+  SlabCtx x;
+  x.L = F.L;
+  x.P = F.P;
+  x.r0 = 0;
+  x.r1 = F.L;
+  x.lrs = F.lrs;
+  x.vpl = F.vpl;
+  x.lane = threadIdx.x & 63;
+  x.wave = wave;
+  x.slot = x.lane >> x.lrs;
+  x.lin = x.lane & ((1 << x.lrs) - 1);
+  x.lam = cp->lam;
+  x.oml = 1.0 - cp->lam;
+  x.sigma = cp->sigma;
+  const int L = F.L;
+  const int64_t soff = F.soff + (int64_t)slab * L * F.P;
+  const int src_i = cp->src, anc_i = cp->anc;
+  const T* src = pick<T>(sb0, sb1, sb2, src_i) + soff;
+  T* dst = pick<T>(sb0, sb1, sb2, cp->dst) + soff;
+  const int anc_kind = anc_i < 0 ? ANC_ZERO : (anc_i == src_i ? ANC_SAME : ANC_SEP);
+  const T* anc = anc_kind == ANC_SEP ? pick<T>(sb0, sb1, sb2, anc_i) + soff : src;
+  const double* alpha = ab + F.aboff + (int64_t)slab * 2 * L;
+  const double* X = fam_x(ab, F);
+  double* rs = rowsum + F.rsoff + (int64_t)slab * L;
+  double* co = colpart + F.cpoff + (int64_t)slab * F.nchunk * L;  // one chunk
+  if (anc_kind == ANC_ZERO)
+    slab_wave<T, MAXVPL, ANC_ZERO, U, C>(x, src, dst, anc, alpha, alpha + L, X, rs, co);
+  else if (anc_kind == ANC_SAME)
+    slab_wave<T, MAXVPL, ANC_SAME, U, C>(x, src, dst, anc, alpha, alpha + L, X, rs, co);
+  else
+    slab_wave<T, MAXVPL, ANC_SEP, U, C>(x, src, dst, anc, alpha, alpha + L, X, rs, co);
 }
 
 template <typename T, int V, int U, int C>
 static void launch_lean(const LaunchArgs& a, int par, hipStream_t st) {
-  hipLaunchKernelGGL((k_slab_pass<T, V, 0, U, C, 0>), dim3(a.slab_grid), dim3(kWG), 0, st,
-                     a.items, a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1],
-                     (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem,
-                     a.bytes_ctr);
+  if (a.nbig > 0)
+    hipLaunchKernelGGL((k_slab_pass<T, V, 0, U, C, 0>), dim3(a.nbig), dim3(kWG), 0, st,
+                       a.items, a.nbig, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1],
+                       (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem);
+  if (a.nsitems > 0)
+    hipLaunchKernelGGL((k_slab_small<T, V, (U & 4) | 2, C>), dim3(a.nsitems), dim3(kWG), 0, st,
+                       a.sitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
+                       a.rowsum[par], a.colpart[par]);
 }
 
 template <typename T, int V, int C, int SU>
 static void launch_heavy(const LaunchArgs& a, int par, hipStream_t st) {
-  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, C, SU>), dim3(a.slab_grid), dim3(kWG), 0, st,
+  hipLaunchKernelGGL((k_slab_pass<T, V, 1, 1, C, SU>), dim3(a.nitems), dim3(kWG), 0, st,
                      a.items, a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1],
-                     (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem,
-                     a.bytes_ctr);
+                     (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem);
 }
 
 template <typename T, int V>

@@ -347,7 +347,9 @@ class Server:
         st = lib().hot_server_submit(self.h, C.byref(prob), tag)
         if st != HOT_OK:
             raise HotError(st, "submit rejected")
-        self._alive[tag] = (mu1, mu2)
+        # the server reads the histograms (and positions) when it admits the
+        # request, possibly much later: keep every buffer alive until then
+        self._alive[tag] = prob._keep
 
     def poll(self, max_results: int = 256):
         res = (Result * max_results)()
