@@ -212,7 +212,11 @@ hot_status hot_aat_solve(hot_ctx *ctx, int32_t m, int32_t n, const double *R,
                          double *y, hot_stream_t stream);
 
 /* Batched solves: many problems (sizes may differ) share every launch; the
- * iteration loop runs device-side in captured HIP graphs.  Submit returns
+ * iteration loop runs device-side in captured HIP graphs.  The batch is
+ * split into a few groups balanced by flow elements (two by default), each
+ * with its own stream and graph, iterated concurrently so that one group's
+ * latency-bound reduce and solve kernels overlap another's streaming slab
+ * pass; with profiling on, the batch runs as one group.  Submit returns
  * once the work is enqueued and a host thread drives it; hot_batch_wait
  * blocks, fills results[count] and frees the handle.  Each problem runs the
  * same kernels and decisions as under hot_solve; the slab-pass chunking

@@ -95,6 +95,7 @@ Tuning default_tuning() {
   t.pingpong = 1;
   t.sep_anchor = 0;
   t.small_side = 64;
+  t.batch_groups = 2;
   return t;
 }
 
@@ -111,7 +112,7 @@ size_t Layout::bytes(uint32_t flags) const {
 }
 
 bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
-                  Layout& lay, std::string& err) {
+                  Layout& lay, std::string& err, int64_t key_elems, int key_pairs) {
   lay = Layout();
   lay.fp32 = fp32;
   lay.elem_size = fp32 ? 4 : 8;
@@ -128,7 +129,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   // workgroup size of the slab pass: enough workgroups to fill the chip,
   // never more than item_elems elements each (or the autotuned size for
   // this total)
-  const int npairs = (int)shapes.size();
+  const int npairs = key_pairs >= 0 ? key_pairs : (int)shapes.size();
+  if (key_elems >= 0) total = key_elems;
   const int64_t item_elems = tune.item_elems_for(total, npairs, fp32);
   int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0, taboff = 0;
   int maxvpl = 1;
@@ -765,7 +767,7 @@ void Workspace::fill_result(int p, hot_result* r, double seconds) const {
 
 struct hot_batch {
   hot_ctx* ctx = nullptr;
-  std::shared_ptr<Workspace> ws;
+  GroupedBatch gb;
   std::thread th;
   hot_status status = HOT_OK;
   double seconds = 0;
@@ -805,6 +807,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.min_items = std::max<int64_t>(1, std::atoll(e));
   e = std::getenv("HOT_SMALL_SIDE");
   if (e) c->tune.small_side = std::max(0, std::atoi(e));
+  e = std::getenv("HOT_BATCH_GROUPS");
+  if (e) c->tune.batch_groups = std::max(1, std::min(4, std::atoi(e)));
   e = std::getenv("HOT_VPL_TARGET");
   if (e) c->tune.vec_per_lane = std::max(1, std::min(8, std::atoi(e)));
   e = std::getenv("HOT_NT_STORE");
@@ -858,7 +862,7 @@ int64_t hot_plan_capacity(int32_t m, int32_t n) {
 namespace hot {
 
 hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
-                          std::shared_ptr<Workspace>& out) {
+                          std::shared_ptr<Workspace>& out, int64_t key_elems, int key_pairs) {
   if (count < 1) {
     ctx->err = "count must be >= 1";
     return HOT_E_INVALID;
@@ -876,7 +880,8 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
   }
   auto ws = std::make_shared<Workspace>();
   std::string err;
-  if (!build_layout(shapes, prec == HOT_FP32_STREAM, ctx->tune, ws->lay, err)) {
+  if (!build_layout(shapes, prec == HOT_FP32_STREAM, ctx->tune, ws->lay, err, key_elems,
+                    key_pairs)) {
     ctx->err = err;
     return HOT_E_INVALID;
   }
@@ -887,7 +892,9 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
     int64_t total = 0;
     for (int p = 0; p < count; ++p)
       total += (int64_t)probs[p].m * probs[p].m * probs[p].n + (int64_t)probs[p].m * probs[p].n * probs[p].n;
-    ws->args.unroll = ctx->tune.unroll_for(total, count, prec == HOT_FP32_STREAM);
+    if (key_elems >= 0) total = key_elems;
+    ws->args.unroll = ctx->tune.unroll_for(total, key_pairs >= 0 ? key_pairs : count,
+                                           prec == HOT_FP32_STREAM);
   }
   ws->args.nt_store = ctx->tune.nt_store;
   // the algorithmic byte count is kept only when the passes are timed
@@ -900,6 +907,141 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
   ws->own_stream = true;
   out = ws;
   return HOT_OK;
+}
+
+hot_status make_groups(hot_ctx* ctx, const hot_problem* probs, int count, int groups,
+                       GroupedBatch& gb) {
+  gb = GroupedBatch();
+  if (count < 1) {
+    ctx->err = "count must be >= 1";
+    return HOT_E_INVALID;
+  }
+  const int G = std::max(1, std::min(groups, count));
+  auto elems = [&](int p) {
+    return (int64_t)probs[p].m * probs[p].m * probs[p].n +
+           (int64_t)probs[p].m * probs[p].n * probs[p].n;
+  };
+  int64_t total = 0;
+  for (int p = 0; p < count; ++p) total += std::max<int64_t>(0, elems(p));
+  // largest first onto the lightest group, then each group in input order
+  std::vector<int> order(count);
+  for (int p = 0; p < count; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return elems(a) > elems(b); });
+  std::vector<int64_t> load(G, 0);
+  std::vector<std::vector<int>> members(G);
+  for (int p : order) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    members[g].push_back(p);
+    load[g] += elems(p);
+  }
+  gb.where.assign(count, {0, 0});
+  for (int g = 0; g < G; ++g) {
+    std::sort(members[g].begin(), members[g].end());
+    std::vector<hot_problem> sub;
+    for (size_t q = 0; q < members[g].size(); ++q) {
+      sub.push_back(probs[members[g][q]]);
+      gb.where[members[g][q]] = {g, (int)q};
+    }
+    std::shared_ptr<Workspace> ws;
+    // every group is laid out with the launch shape of the whole batch
+    const hot_status s = make_workspace(ctx, sub.data(), (int)sub.size(), ws, total, count);
+    if (s != HOT_OK) return s;
+    gb.wss.push_back(ws);
+  }
+  return HOT_OK;
+}
+
+// Iterate several workspaces (disjoint problems) concurrently, each on its
+// own stream with two captured graphs in flight, until all have stopped.
+hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Workspace>>& wss,
+                          int64_t max_graphs) {
+  if (wss.size() == 1 || !use_graphs() || wss[0]->profile) {
+    for (const auto& ws : wss) {
+      const hot_status s = ws->run(ctx, ws->stream, max_graphs);
+      if (s != HOT_OK) return s;
+    }
+    return HOT_OK;
+  }
+  struct St {
+    Workspace* ws;
+    hipEvent_t ev[2];
+    PairCtl* hc[2];
+    int64_t launched;
+    int cur;
+    bool done;
+  };
+  std::vector<St> sts;
+  hot_status result = HOT_OK;
+  for (const auto& w : wss) {
+    St t;
+    t.ws = w.get();
+    t.ev[0] = t.ev[1] = nullptr;
+    const size_t np = w->lay.geo.size();
+    t.hc[0] = w->host_ctl;
+    t.hc[1] = w->host_ctl + np;
+    t.launched = 0;
+    t.cur = 0;
+    t.done = false;
+    sts.push_back(t);
+  }
+  auto launch_one = [&](St& t, int slot) -> hipError_t {
+    hipError_t e = hipGraphLaunch(t.ws->graph_exec, t.ws->stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(t.hc[slot], t.ws->ctl_d, t.ws->lay.geo.size() * sizeof(PairCtl),
+                       hipMemcpyDeviceToHost, t.ws->stream);
+    if (e != hipSuccess) return e;
+    ++t.launched;
+    t.ws->iterations_launched = t.launched * kGraphIters;
+    return hipEventRecord(t.ev[slot], t.ws->stream);
+  };
+  hipError_t e = hipSuccess;
+  for (St& t : sts) {
+    if ((result = t.ws->ensure_graph(ctx, t.ws->stream)) != HOT_OK) break;
+    for (int q = 0; q < 2 && e == hipSuccess; ++q)
+      e = hipEventCreateWithFlags(&t.ev[q], hipEventDisableTiming);
+    if (e == hipSuccess) e = launch_one(t, 0);
+    if (e == hipSuccess && t.launched < max_graphs) e = launch_one(t, 1);
+    if (e != hipSuccess) break;
+  }
+  bool busy = result == HOT_OK && e == hipSuccess;
+  while (busy) {
+    busy = false;
+    for (St& t : sts) {
+      if (t.done) continue;
+      // graphs k (slot cur) and k+1 (slot cur^1) are queued; wait for k
+      if ((e = hipEventSynchronize(t.ev[t.cur])) != hipSuccess) break;
+      bool running = false;
+      for (size_t p = 0; p < t.ws->lay.geo.size(); ++p)
+        if (t.hc[t.cur][p].status == ST_RUNNING) running = true;
+      if (!running || t.launched >= max_graphs) {
+        t.done = true;
+        continue;
+      }
+      if ((e = launch_one(t, t.cur)) != hipSuccess) break;  // graph k+2 reuses slot cur
+      t.cur ^= 1;
+      busy = true;
+    }
+    if (e != hipSuccess) break;
+  }
+  if (result == HOT_OK && e != hipSuccess) {
+    ctx->err = std::string("iteration launch failed: ") + hipGetErrorString(e);
+    result = HOT_E_DEVICE;
+  }
+  for (St& t : sts) {
+    (void)hipStreamSynchronize(t.ws->stream);
+    for (int q = 0; q < 2; ++q)
+      if (t.ev[q]) (void)hipEventDestroy(t.ev[q]);
+    if (result == HOT_OK) {
+      // after whole graphs the latest control blocks are ctl[0]
+      e = hipMemcpy(t.ws->host_ctl, t.ws->ctl_d, t.ws->lay.geo.size() * sizeof(PairCtl),
+                    hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        ctx->err = std::string("status copy failed: ") + hipGetErrorString(e);
+        result = HOT_E_DEVICE;
+      }
+    }
+  }
+  return result;
 }
 
 }  // namespace hot
@@ -994,27 +1136,33 @@ hot_status hot_batch_submit(hot_ctx* ctx, const hot_problem* probs, int32_t coun
                             hot_stream_t stream, hot_batch** out) {
   if (!ctx || !probs || !out || count < 1) return HOT_E_INVALID;
   *out = nullptr;
-  std::shared_ptr<Workspace> ws;
+  GroupedBatch gb;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return HOT_E_DEVICE;
-    hot_status s = make_workspace(ctx, probs, count, ws);
+    // timed (profiling) solves run the batch as one launch per pass, so each
+    // timed slab pass is the whole batch's; otherwise concurrent groups
+    hot_status s = make_groups(ctx, probs, count, ctx->profiling ? 1 : ctx->tune.batch_groups, gb);
     if (s != HOT_OK) return s;
-    hipStream_t st = ws->stream;
+    // order every group after the caller's stream
     hipEvent_t ev;
     HIPCK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     HIPCK(hipEventRecord(ev, (hipStream_t)stream));
-    HIPCK(hipStreamWaitEvent(st, ev, 0));
+    for (const auto& ws : gb.wss) HIPCK(hipStreamWaitEvent(ws->stream, ev, 0));
     (void)hipEventDestroy(ev);
-    s = ws->setup(ctx, probs, count, st);
-    if (s != HOT_OK) return s;
+    std::vector<std::vector<hot_problem>> sub(gb.wss.size());
+    for (int p = 0; p < count; ++p) sub[gb.where[p].first].push_back(probs[p]);
+    for (size_t g = 0; g < gb.wss.size(); ++g) {
+      s = gb.wss[g]->setup(ctx, sub[g].data(), (int)sub[g].size(), gb.wss[g]->stream);
+      if (s != HOT_OK) return s;
+    }
   }
   int64_t max_it = 1;
   for (int p = 0; p < count; ++p) max_it = std::max<int64_t>(max_it, probs[p].max_iter);
   hot_batch* b = new hot_batch();
   b->ctx = ctx;
-  b->ws = ws;
+  b->gb = std::move(gb);
   b->count = count;
   const int64_t max_graphs = max_it * 2 / kGraphIters + 8;
   const int dev = ctx->device;
@@ -1022,11 +1170,12 @@ hot_status hot_batch_submit(hot_ctx* ctx, const hot_problem* probs, int32_t coun
     (void)hipSetDevice(dev);
     const auto t0 = std::chrono::steady_clock::now();
     hot_ctx tmp;  // private error sink for the worker thread
-    b->status = b->ws->run(&tmp, b->ws->stream, max_graphs);
+    b->status = run_concurrent(&tmp, b->gb.wss, max_graphs);
     {
       std::lock_guard<std::mutex> lk(b->ctx->mu);
       if (b->status != HOT_OK) b->ctx->err = tmp.err;
-      else collect_profile(b->ctx, *b->ws);
+      else
+        for (const auto& ws : b->gb.wss) collect_profile(b->ctx, *ws);
     }
     b->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   });
@@ -1039,7 +1188,8 @@ hot_status hot_batch_wait(hot_batch* b, hot_result* results) {
   if (b->th.joinable()) b->th.join();
   hot_status s = b->status;
   if (s == HOT_OK && results)
-    for (int p = 0; p < b->count; ++p) b->ws->fill_result(p, &results[p], b->seconds);
+    for (int p = 0; p < b->count; ++p)
+      b->gb.wss[b->gb.where[p].first]->fill_result(b->gb.where[p].second, &results[p], b->seconds);
   delete b;
   return s;
 }

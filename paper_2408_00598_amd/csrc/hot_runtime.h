@@ -29,6 +29,7 @@ struct Tuning {
                         // every pass after the first restart does
   int small_side;       // families with slab side <= this run plain-update passes
                         // wave-per-slab (whole slab per wave, no block barriers)
+  int batch_groups;     // concurrent groups (streams) a batch is split into
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
@@ -96,8 +97,10 @@ struct Layout {
   size_t bytes(uint32_t flags = 0) const;  // device bytes; flags: HOT_FLAG_* of the problems
 };
 
+// key_elems / key_pairs >= 0: look the launch shape up under these totals
+// (a group of a larger batch uses the batch's entry)
 bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
-                  Layout& lay, std::string& err);
+                  Layout& lay, std::string& err, int64_t key_elems = -1, int key_pairs = -1);
 
 struct Workspace {
   int device = 0;
@@ -150,7 +153,20 @@ struct Workspace {
 };
 
 hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
-                          std::shared_ptr<Workspace>& out);
+                          std::shared_ptr<Workspace>& out, int64_t key_elems = -1,
+                          int key_pairs = -1);
+
+// A batch split into groups of problems (balanced by flow elements), one
+// workspace and stream each, iterated concurrently so that one group's
+// latency-bound pair kernels overlap another group's streaming slab pass.
+struct GroupedBatch {
+  std::vector<std::shared_ptr<Workspace>> wss;
+  std::vector<std::pair<int, int>> where;  // problem -> (group, index in group)
+};
+hot_status make_groups(hot_ctx* ctx, const hot_problem* probs, int count, int groups,
+                       GroupedBatch& gb);
+hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Workspace>>& wss,
+                          int64_t max_graphs);
 
 }  // namespace hot
 

@@ -8,6 +8,8 @@
 // device architecture, precision and size class.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -91,26 +93,26 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
     tmp.tune.sep_anchor = 1;  // time the three-stream passes of the steady state
     tmp.profiling = false;
     // whole iterations (slab pass, reduce, solve) as the solver runs them:
-    // captured graphs, hipEvents around the run; the first run captures
-    std::shared_ptr<Workspace> ws;
+    // the batch's groups on their streams, captured graphs, wall clock
+    // around the run after the set-up has synchronised; the first run
+    // captures the graphs
+    GroupedBatch gb;
     double secs = 0.0;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    status = make_workspace(&tmp, pr.data(), count, ws);
-    for (int q = 0; q < 2 && status == HOT_OK; ++q)
-      if (hipEventCreate(&ev[q]) != hipSuccess) status = HOT_E_DEVICE;
+    status = make_groups(&tmp, pr.data(), count, tmp.tune.batch_groups, gb);
+    std::vector<std::vector<hot_problem>> sub(gb.wss.size());
+    if (status == HOT_OK)
+      for (int p = 0; p < count; ++p) sub[gb.where[p].first].push_back(pr[p]);
     for (int rep = 0; rep < 2 && status == HOT_OK; ++rep) {
-      status = ws->setup(&tmp, pr.data(), count, ws->stream);
-      if (status == HOT_OK && hipEventRecord(ev[0], ws->stream) != hipSuccess) status = HOT_E_DEVICE;
-      if (status == HOT_OK) status = ws->run(&tmp, ws->stream, (int64_t)iters * 2 / kGraphIters + 8);
-      if (status == HOT_OK && (hipEventRecord(ev[1], ws->stream) != hipSuccess ||
-                               hipEventSynchronize(ev[1]) != hipSuccess))
-        status = HOT_E_DEVICE;
-      float ms = 0.0f;
-      if (status == HOT_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) status = HOT_E_DEVICE;
-      secs = (double)ms * 1e-3 / (double)iters;
+      for (size_t g = 0; g < gb.wss.size() && status == HOT_OK; ++g)
+        status = gb.wss[g]->setup(&tmp, sub[g].data(), (int)sub[g].size(), gb.wss[g]->stream);
+      for (size_t g = 0; g < gb.wss.size() && status == HOT_OK; ++g)
+        if (hipStreamSynchronize(gb.wss[g]->stream) != hipSuccess) status = HOT_E_DEVICE;
+      const auto t0 = std::chrono::steady_clock::now();
+      if (status == HOT_OK)
+        status = run_concurrent(&tmp, gb.wss, (int64_t)iters * 2 / kGraphIters + 8);
+      secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() /
+             (double)iters;
     }
-    for (int q = 0; q < 2; ++q)
-      if (ev[q]) (void)hipEventDestroy(ev[q]);
     if (status != HOT_OK) {
       ctx->err = "autotune: " + (tmp.err.empty() ? std::string("device error") : tmp.err);
       break;
