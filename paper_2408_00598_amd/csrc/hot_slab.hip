@@ -286,12 +286,20 @@ __device__ inline void slab_item(
   for (int q = threadIdx.x; q < L; q += kWG)
     cpo[q] = (lds_col[q] + lds_col[S + q]) + (lds_col[2 * S + q] + lds_col[3 * S + q]);
   if (HEAVY && mode == MODE_CHECK) {
+    // all partials at once: wave sums, one barrier, then the fixed order
+    // (w0 + w1) + (w2 + w3) per partial
     double* ko = kitem + (int64_t)itm.kslot * kKI;
     const int nq = su ? 7 : 6;
-    double r[7];
-    for (int q = 0; q < nq; ++q) r[q] = block_sum(kk[q], red);
-    if (threadIdx.x == 0)
-      for (int q = 0; q < nq; ++q) ko[q] = r[q];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const double v = wave_sum(kk[q]);
+      if (q < nq && x.lane == 0) red[x.wave * 8 + q] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nq) {
+      const int q = threadIdx.x;
+      ko[q] = (red[q] + red[8 + q]) + (red[16 + q] + red[24 + q]);
+    }
   }
 }
 
@@ -309,7 +317,7 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
   __shared__ double lds_col[4 * S];
   __shared__ double lds_beta[S];
   __shared__ double lds_x[C ? S : 1];
-  __shared__ double red[4];
+  __shared__ double red[32];
   if ((int)blockIdx.x < nitems)
     slab_item<T, MAXVPL, HEAVY, U, C, SU>(blockIdx.x, items, geo, ctl, sb0, sb1, sb2, sbx, ab, rowsum,
                                       colpart, kitem, lds_col, lds_beta, lds_x, red);
