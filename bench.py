@@ -267,12 +267,18 @@ def main():
     ctx = hot.Context(0)
     kw = dict(tol=tol, max_iter=1000000, prec=prec)
 
+    plan_stats = []
+
     def step():
         if len(dpairs) == 1:
             res, sol = ctx.solve(*dpairs[0], keep=args.plan, **kw)
             out = [res]
             if args.plan:
-                sol.recover_plan()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                src, _, _, err = sol.recover_plan()
+                torch.cuda.synchronize()
+                plan_stats.append((time.perf_counter() - t1, int(src.numel()), err))
                 sol.free()
             return out
         return ctx.batch_solve(dpairs, **kw)
@@ -331,6 +337,12 @@ def main():
                         "kkt_max": float(max(r["kkt"] for r in results)),
                         "converged": int(sum(r["status"] == 0 for r in results))},
     }
+    if plan_stats:
+        secs = [p[0] for p in plan_stats]
+        out["plan"] = {"seconds_mean": float(np.mean(secs)), "seconds_min": float(np.min(secs)),
+                       "nnz": plan_stats[-1][1], "marginal_l1_raw": plan_stats[-1][2][:2],
+                       "marginal_l1_repaired": plan_stats[-1][2][2:],
+                       "note": "Algorithm 1 + repair on the solved pair, inside each step"}
     if not args.no_fp64_plain and len(dpairs) > 1:
         # plain per-pair FP64 solves on the same GPU: two pairs per grid side
         by_side = {}
