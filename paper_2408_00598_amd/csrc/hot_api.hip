@@ -261,7 +261,18 @@ namespace hot {
 
 Workspace::~Workspace() { release(); }
 
+void Workspace::drop_retired() {
+  for (auto& g : retired) {
+    if (g.second) (void)hipGraphExecDestroy(g.second);
+    if (g.first) (void)hipGraphDestroy(g.first);
+  }
+  retired.clear();
+}
+
 void Workspace::release() {
+  drop_retired();
+  if (stage_h) (void)hipHostFree(stage_h);
+  stage_h = nullptr;
   if (quantum_event) (void)hipEventDestroy(quantum_event);
   quantum_event = nullptr;
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -302,6 +313,21 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   if ((st = A((void**)&items_d, lay.items.size() * sizeof(SlabItem))) != HOT_OK) return st;
   if ((st = A((void**)&sitems_d, std::max<size_t>(lay.sitems.size(), 1) * sizeof(SmallItem))) != HOT_OK)
     return st;
+  const size_t n_it = std::max<size_t>(lay.items.size(), 1) * sizeof(SlabItem);
+  const size_t n_si = std::max<size_t>(lay.sitems.size(), 1) * sizeof(SmallItem);
+  const size_t n_bl = std::max<size_t>(lay.blocks.size(), 1) * sizeof(PBlock);
+  const size_t n_sb = std::max<size_t>(lay.sblocks.size(), 1) * sizeof(PBlock);
+  if (lay.geo.size() > 1) {  // compacted launch tables (batches only)
+    if ((st = A((void**)&items_c, n_it)) != HOT_OK) return st;
+    if ((st = A((void**)&sitems_c, n_si)) != HOT_OK) return st;
+    if ((st = A((void**)&blocks_c, n_bl)) != HOT_OK) return st;
+    if ((st = A((void**)&sblocks_c, n_sb)) != HOT_OK) return st;
+    if (hipHostMalloc(&stage_h, n_it + n_si + n_bl + n_sb) != hipSuccess) {
+      stage_h = nullptr;
+      if (ctx) ctx->err = "hipHostMalloc failed";
+      return HOT_E_NOMEM;
+    }
+  }
   if ((st = A((void**)&blocks_d, lay.blocks.size() * sizeof(PBlock))) != HOT_OK) return st;
   if ((st = A((void**)&sblocks_d, lay.sblocks.size() * sizeof(PBlock))) != HOT_OK) return st;
   if ((st = A((void**)&geo_d, lay.geo.size() * sizeof(PairGeo))) != HOT_OK) return st;
@@ -338,6 +364,7 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   args.fp32 = lay.fp32;
   args.maxvpl = lay.maxvpl;
   args.bytes_ctr = bytes_ctr;
+  launch_pairs = (int)lay.geo.size();
   return HOT_OK;
 }
 
@@ -386,6 +413,8 @@ namespace hot {
 // blocks, copy tables and clear the state.  Synchronises `st` once.
 hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st) {
   const size_t np = lay.geo.size();
+  restore_tables();  // (no graph is in flight between runs)
+  drop_retired();
   std::vector<const double*> ptrs(2 * np);
   std::vector<int64_t> lens(2 * np);
   for (size_t p = 0; p < np; ++p) {
@@ -704,6 +733,82 @@ hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_gra
   return result;
 }
 
+// Full launch tables (every problem of the workspace); retires a graph
+// captured with compacted ones.
+void Workspace::restore_tables() {
+  const bool compacted = args.items != items_d;
+  args.items = items_d;
+  args.nitems = (int)lay.items.size();
+  args.nbig = (int)lay.nbig;
+  args.sitems = sitems_d;
+  args.nsitems = (int)lay.sitems.size();
+  args.blocks = blocks_d;
+  args.nblocks = (int)lay.blocks.size();
+  args.sblocks = sblocks_d;
+  args.nsblocks = (int)lay.sblocks.size();
+  launch_pairs = (int)lay.geo.size();
+  if (compacted && graph_exec) {
+    retired.push_back({graph, graph_exec});
+    graph = nullptr;
+    graph_exec = nullptr;
+  }
+}
+
+// Between graphs: when at most half of the problems the current tables
+// cover are still running, launch only those from now on (their results do
+// not depend on which other problems share a launch).  The new tables are
+// uploaded on the workspace's stream, so graphs still in flight finish
+// with the old ones first; the graph is re-captured with the new tables.
+hot_status Workspace::compact(hot_ctx* ctx, const PairCtl* hc) {
+  if (!stage_h) return HOT_OK;
+  const size_t np = lay.geo.size();
+  std::vector<char> act(np, 0);
+  int active = 0;
+  for (size_t p = 0; p < np; ++p)
+    if (hc[p].status == ST_RUNNING) {
+      act[p] = 1;
+      ++active;
+    }
+  if (active == 0 || 2 * active > launch_pairs) return HOT_OK;
+  SlabItem* it = (SlabItem*)stage_h;
+  SmallItem* si = (SmallItem*)((char*)stage_h + std::max<size_t>(lay.items.size(), 1) * sizeof(SlabItem));
+  PBlock* bl = (PBlock*)((char*)si + std::max<size_t>(lay.sitems.size(), 1) * sizeof(SmallItem));
+  PBlock* sb = bl + std::max<size_t>(lay.blocks.size(), 1);
+  int nit = 0, nbig = 0, nsi = 0, nbl = 0, nsb = 0;
+  for (const SlabItem& x : lay.items)  // block plain-update items first, as in the layout
+    if (act[x.pair] && !x.small) it[nit++] = x;
+  nbig = nit;
+  for (const SlabItem& x : lay.items)
+    if (act[x.pair] && x.small) it[nit++] = x;
+  for (const SmallItem& x : lay.sitems)
+    if (act[x.pair]) si[nsi++] = x;
+  for (const PBlock& x : lay.blocks)
+    if (act[x.pair]) bl[nbl++] = x;
+  for (const PBlock& x : lay.sblocks)
+    if (act[x.pair]) sb[nsb++] = x;
+  HIPCK(hipMemcpyAsync(items_c, it, (size_t)std::max(nit, 1) * sizeof(SlabItem),
+                       hipMemcpyHostToDevice, stream));
+  if (nsi > 0)
+    HIPCK(hipMemcpyAsync(sitems_c, si, (size_t)nsi * sizeof(SmallItem), hipMemcpyHostToDevice,
+                         stream));
+  HIPCK(hipMemcpyAsync(blocks_c, bl, (size_t)nbl * sizeof(PBlock), hipMemcpyHostToDevice, stream));
+  HIPCK(hipMemcpyAsync(sblocks_c, sb, (size_t)nsb * sizeof(PBlock), hipMemcpyHostToDevice, stream));
+  if (graph_exec) retired.push_back({graph, graph_exec});
+  graph = nullptr;
+  graph_exec = nullptr;
+  args.items = items_c;
+  args.nitems = nit;
+  args.nbig = nbig;
+  args.sitems = sitems_c;
+  args.nsitems = nsi;
+  args.blocks = blocks_c;
+  args.nblocks = nbl;
+  args.sblocks = sblocks_c;
+  args.nsblocks = nsb;
+  launch_pairs = active;
+  return ensure_graph(ctx, stream);
+}
+
 hot_status Workspace::ensure_graph(hot_ctx* ctx, hipStream_t st) {
   if (graph_exec) return HOT_OK;
   HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -1017,11 +1122,12 @@ hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Worksp
         t.done = true;
         continue;
       }
+      if ((result = t.ws->compact(ctx, t.hc[t.cur])) != HOT_OK) break;
       if ((e = launch_one(t, t.cur)) != hipSuccess) break;  // graph k+2 reuses slot cur
       t.cur ^= 1;
       busy = true;
     }
-    if (e != hipSuccess) break;
+    if (e != hipSuccess || result != HOT_OK) break;
   }
   if (result == HOT_OK && e != hipSuccess) {
     ctx->err = std::string("iteration launch failed: ") + hipGetErrorString(e);
@@ -1029,6 +1135,7 @@ hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Worksp
   }
   for (St& t : sts) {
     (void)hipStreamSynchronize(t.ws->stream);
+    t.ws->drop_retired();
     for (int q = 0; q < 2; ++q)
       if (t.ev[q]) (void)hipEventDestroy(t.ev[q]);
     if (result == HOT_OK) {

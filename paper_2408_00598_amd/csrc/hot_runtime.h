@@ -129,6 +129,19 @@ struct Workspace {
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long* bytes_ctr = nullptr;
   std::vector<double> tab_host;  // cost tables uploaded by setup
+  // launch tables restricted to the problems still running (a batch whose
+  // problems have mostly stopped launches only the rest): device copies,
+  // pinned host staging, problems the current tables cover, retired graphs
+  SlabItem* items_c = nullptr;
+  SmallItem* sitems_c = nullptr;
+  PBlock* blocks_c = nullptr;
+  PBlock* sblocks_c = nullptr;
+  void* stage_h = nullptr;
+  int launch_pairs = 0;
+  std::vector<std::pair<hipGraph_t, hipGraphExec_t>> retired;
+  hot_status compact(hot_ctx* ctx, const PairCtl* hc);
+  void restore_tables();
+  void drop_retired();
   int graph_variant = 0;         // slab kernel variant the graph was captured with
   void* sbx = nullptr;           // sigma re-balancing buffers, allocated on first use
   double* abY = nullptr;
