@@ -89,3 +89,28 @@ def test_zero_mass_bins(oracle):
     assert abs(r["primal_obj"] - o["primal_obj"]) <= 1e-6 * abs(o["primal_obj"])
     src, dst, mass, err = sol.recover_plan()
     assert err[2] <= 1e-12 and err[3] <= 1e-12
+
+
+def test_batch_with_early_finishers_equals_alone():
+    """Most problems of the batch stop after a few checks (identical source and
+    target), so the launch tables are rebuilt for the remaining ones while they
+    iterate; every result still equals its solo solve bit for bit."""
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    rng = np.random.default_rng(77)
+    slow = workloads.batch_pairs(4, sides=(12, 16))
+    fast = []
+    for n in (8, 10, 12, 14, 16, 20, 8, 10):
+        h = rng.uniform(0.1, 1, (n, n))
+        h /= h.sum()
+        fast.append((h, h.copy()))
+    pairs = fast[:4] + slow[:2] + fast[4:] + slow[2:]
+    c = ctx()
+    dp = [(dev(a), dev(b)) for a, b in pairs]
+    batch = c.batch_solve(dp, tol=1e-6, max_iter=200000)
+    iters = [r["iters"] for r in batch]
+    assert max(iters) > 4 * min(iters)
+    for (a, b), rb in zip(dp, batch):
+        ra, _ = c.solve(a, b, tol=1e-6, max_iter=200000)
+        for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
+            assert ra[key] == rb[key], (key, ra[key], rb[key])
