@@ -20,7 +20,7 @@ def test_autotune_and_cache(tmp_path, oracle):
     cache = str(tmp_path / "tune.jsonl")
     best = c.autotune(dp, iters=20, cache_path=cache, prec=hot.HOT_FP32_STREAM)
     assert best["item_elems"] >= 2048 and best["unroll"] in (1, 2)
-    assert best["slab_us_per_iter"] > 0 and best["default_us_per_iter"] > 0
+    assert best["us_per_iter"] > 0 and best["default_us_per_iter"] > 0
     line = json.loads(open(cache).read().strip().splitlines()[-1])
     assert line["item_elems"] == best["item_elems"] and line["fp32"] == 1
     c2 = hot.Context(0)
