@@ -96,6 +96,7 @@ Tuning default_tuning() {
   t.sep_anchor = 0;
   t.small_side = 64;
   t.batch_groups = 2;
+  t.fuse = 1;
   return t;
 }
 
@@ -912,6 +913,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.min_items = std::max<int64_t>(1, std::atoll(e));
   e = std::getenv("HOT_SMALL_SIDE");
   if (e) c->tune.small_side = std::max(0, std::atoi(e));
+  e = std::getenv("HOT_FUSE");
+  if (e) c->tune.fuse = std::atoi(e) != 0;
   e = std::getenv("HOT_BATCH_GROUPS");
   if (e) c->tune.batch_groups = std::max(1, std::min(4, std::atoi(e)));
   e = std::getenv("HOT_VPL_TARGET");
@@ -1002,6 +1005,7 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
                                            prec == HOT_FP32_STREAM);
   }
   ws->args.nt_store = ctx->tune.nt_store;
+  ws->args.fuse = ctx->tune.fuse;
   // the algorithmic byte count is kept only when the passes are timed
   ws->args.bytes_ctr = ws->profile ? ws->bytes_ctr : nullptr;
   if (s != HOT_OK) return s;

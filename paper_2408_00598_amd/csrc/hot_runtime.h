@@ -30,6 +30,7 @@ struct Tuning {
   int small_side;       // families with slab side <= this run plain-update passes
                         // wave-per-slab (whole slab per wave, no block barriers)
   int batch_groups;     // concurrent groups (streams) a batch is split into
+  int fuse;             // default for one slab kernel for every pass
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
@@ -77,6 +78,7 @@ struct LaunchArgs {
   int nt_store = 0;   // non-temporal stores of the new state
   int coord = 0;      // some pair has non-uniform bins: slab passes read positions
   int su = 0;         // some pair re-balances sigma at restarts
+  int fuse = 0;       // one slab kernel for plain, check and restart passes
   void* sbx = nullptr;      // x_bar of the last restart (sigma re-balancing), else null
   double* abY = nullptr;    // alpha / beta of the last restart (sigma re-balancing)
   unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes

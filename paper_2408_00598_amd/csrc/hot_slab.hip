@@ -54,7 +54,7 @@ struct SlabCtx {
 // ||x_bar - X||^2; restart passes write x_bar to xr and the new state
 // x_bar / sigma_new + z_bar = (sigma_old / sigma_new)(s - g) + max(0, 2g - s).
 template <typename T, int MAXVPL, int MODE, int ANC, int U, int C, int SU>
-__device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
+__device__ __forceinline__ void slab_rows(const SlabCtx& x, const T* __restrict__ src,
                                  T* __restrict__ dst, const T* __restrict__ anc,
                                  T* __restrict__ xr,
                                  const double* __restrict__ alpha, const double* __restrict__ bl,
@@ -159,11 +159,16 @@ __device__ inline void slab_rows(const SlabCtx& x, const T* __restrict__ src,
   }
 }
 
-// HEAVY = 0: plain update passes; HEAVY = 1: check and restart passes.  Both
-// kernels are launched every iteration; a workgroup whose pair is in the
-// other kind of pass exits at once.
+// HEAVY = 0: plain update passes; HEAVY = 1: check and restart passes (when
+// both are launched every iteration, a workgroup whose pair is in the other
+// kind of pass exits at once).  HEAVY = 2: every pass kind in one kernel,
+// check and restart rows streamed one row step at a time as in HEAVY = 1;
+// its register count stays that of the plain kernel, and the launch it saves
+// is worth 2-4% of a solve.  The three are forced inline into their kernels:
+// a second caller would otherwise turn slab_item into a real call, which
+// more than doubles the register count.
 template <typename T, int MAXVPL, int HEAVY, int U, int C, int SU>
-__device__ inline void slab_item(
+__device__ __forceinline__ void slab_item(
     int item, const SlabItem* __restrict__ items, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, T* __restrict__ sb0, T* __restrict__ sb1,
     T* __restrict__ sb2, T* __restrict__ sbx, const double* __restrict__ ab,
@@ -177,8 +182,11 @@ __device__ inline void slab_item(
   const int status = cp->status;
   const int mode = cp->mode;
   if (status != ST_RUNNING) return;
-  if (HEAVY ? (mode != MODE_CHECK && mode != MODE_RESTART) : (mode != MODE_NORMAL)) return;
-  if (!HEAVY && itm.small) return;  // (not launched: small items follow the first nbig)
+  if (HEAVY == 0 && mode != MODE_NORMAL) return;
+  if (HEAVY == 1 && mode != MODE_CHECK && mode != MODE_RESTART) return;
+  if (mode != MODE_NORMAL && mode != MODE_CHECK && mode != MODE_RESTART) return;
+  const bool plain = mode == MODE_NORMAL;
+  if (plain && itm.small) return;  // (the wave-per-slab kernel runs these)
   // (uniform per workgroup: every thread reads the same control block)
   const FamGeo F = geo[itm.pair].f[itm.fam];
   SlabCtx x;
@@ -228,13 +236,19 @@ __device__ inline void slab_item(
 #pragma unroll
     for (int e = 0; e < W; ++e) colacc[v][e] = 0.0;
   double kk[7] = {0, 0, 0, 0, 0, 0, 0};
+  // check and restart rows: one row step at a time; plain rows: the
+  // launch's unroll and store kind
+  constexpr int UH = HEAVY == 2 ? 1 : U;
 #define HOT_ROWS(MODE_, ANC_, SU_)                                                        \
-  slab_rows<T, MAXVPL, MODE_, ANC_, U, C, SU_>(x, src, dst, anc, xr, alpha, lds_beta, lds_x, \
-                                               colacc, rs, kk)
-  if (!HEAVY) {
+  slab_rows<T, MAXVPL, MODE_, ANC_, (MODE_ == MODE_NORMAL ? U : UH), C, SU_>(             \
+      x, src, dst, anc, xr, alpha, lds_beta, lds_x, colacc, rs, kk)
+  if (HEAVY != 1 && plain) {
     if (anc_kind == ANC_ZERO) HOT_ROWS(MODE_NORMAL, ANC_ZERO, 0);
     else if (anc_kind == ANC_SAME) HOT_ROWS(MODE_NORMAL, ANC_SAME, 0);
     else HOT_ROWS(MODE_NORMAL, ANC_SEP, 0);
+  } else if (HEAVY == 0) {
+    // (not reached: the mode test above; keeps the check and restart code
+    // out of the plain kernel)
   } else if (mode == MODE_CHECK) {
     bool done = false;
     if constexpr (SU) {
@@ -334,7 +348,7 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
 // element is the block pass's, term for term.
 // ---------------------------------------------------------------------------
 template <typename T, int MAXVPL, int ANC, int U, int C>
-__device__ inline void slab_wave(const SlabCtx& x, const T* __restrict__ src,
+__device__ __forceinline__ void slab_wave(const SlabCtx& x, const T* __restrict__ src,
                                  T* __restrict__ dst, const T* __restrict__ anc,
                                  const double* __restrict__ alpha,
                                  const double* __restrict__ beta, const double* __restrict__ X,
@@ -493,8 +507,31 @@ static void launch_heavy(const LaunchArgs& a, int par, hipStream_t st) {
                      (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem);
 }
 
+// Every pass of the block items in one kernel (plain, check, restart), plus
+// the wave-per-slab kernel for small slabs.
+template <typename T, int V, int U, int C, int SU>
+static void launch_fused(const LaunchArgs& a, int par, hipStream_t st) {
+  hipLaunchKernelGGL((k_slab_pass<T, V, 2, U, C, SU>), dim3(a.nitems), dim3(kWG), 0, st,
+                     a.items, a.nitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1],
+                     (T*)a.sb[2], (T*)a.sbx, a.ab, a.rowsum[par], a.colpart[par], a.kitem);
+  if (a.nsitems > 0)
+    hipLaunchKernelGGL((k_slab_small<T, V, (U & 4) | 2, C>), dim3(a.nsitems), dim3(kWG), 0, st,
+                       a.sitems, a.geo, a.ctl[par], (T*)a.sb[0], (T*)a.sb[1], (T*)a.sb[2], a.ab,
+                       a.rowsum[par], a.colpart[par]);
+}
+
 template <typename T, int V>
 static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
+  if (a.fuse && !a.coord && !a.su) {
+    const int u = (a.unroll >= 2 ? 2 : 1) | (a.nt_store ? 4 : 0);
+    switch (u) {
+      case 1: launch_fused<T, V, 1, 0, 0>(a, par, st); break;
+      case 2: launch_fused<T, V, 2, 0, 0>(a, par, st); break;
+      case 5: launch_fused<T, V, 5, 0, 0>(a, par, st); break;
+      default: launch_fused<T, V, 6, 0, 0>(a, par, st); break;
+    }
+    return;
+  }
   if (a.coord) {  // non-uniform bins: positions from LDS, one row per wave step
     if (a.nt_store) launch_lean<T, V, 5, 1>(a, par, st);
     else launch_lean<T, V, 1, 1>(a, par, st);

@@ -23,6 +23,37 @@ def test_batch_equals_alone_bitwise():
                 assert ra[key] == rb[key], (key, ra[key], rb[key])
 
 
+def test_fused_and_split_slab_kernels_bitwise(monkeypatch):
+    """One slab kernel for every pass kind and the split plain / check-restart
+    kernels do the same arithmetic in the same order: identical results and
+    states, for block and wave-per-slab families, both precisions."""
+    need_gpu()
+    import torch
+    from paper_2408_00598_amd import hot, workloads
+    pairs = workloads.batch_pairs(6, sides=(24, 48, 96, 130))
+    dp = [(dev(a), dev(b)) for a, b in pairs]
+    ctxs = []
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("HOT_FUSE", fuse)
+        ctxs.append(hot.Context(0))
+    for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
+        rs = [c.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec) for c in ctxs]
+        for ra, rb in zip(*rs):
+            for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
+                assert ra[key] == rb[key], (prec, key, ra[key], rb[key])
+        rng = np.random.default_rng(workloads.seed_for(0, 130))
+        a = dev(workloads.gaussian_blobs(130, 130, 3, rng))
+        b = dev(workloads.gaussian_blobs(130, 130, 3, rng))
+        outs = []
+        for c in ctxs:
+            r, sol = c.solve(a, b, keep=True, max_iter=137, prec=prec,
+                             flags=hot.HOT_FLAG_RESTART | hot.HOT_FLAG_FIXED_ITERS)
+            outs.append((r, [t.cpu() for t in sol.export()]))
+        assert outs[0][0]["primal_obj"] == outs[1][0]["primal_obj"]
+        for t0, t1 in zip(outs[0][1], outs[1][1]):
+            assert torch.equal(t0, t1)
+
+
 def test_batch_matches_oracle(oracle):
     need_gpu()
     from paper_2408_00598_amd import workloads
