@@ -63,22 +63,32 @@ def launch_key(tuned):
 
 
 def make_workload(name, pairs):
+    """(pairs, tol, precision, description without precision and tolerance)."""
     from paper_2408_00598_amd import hot, workloads
     if name == "batched":
         return (workloads.batch_pairs(pairs), 1e-4, hot.HOT_FP32_STREAM,
                 f"batched {pairs} pairs, n~U{{32,48,64,96,128}}, 50% 1-5 Gaussian blobs / 50% "
-                "U(0,1) noise, FP32 streams + FP64 reductions, rel KKT 1e-4")
+                "U(0,1) noise")
     if name == "pair128":
         return ([workloads.pair_medium("blobs")], 1e-4, hot.HOT_FP32_STREAM,
-                "one 128x128 pair, 5 Gaussian blobs + floor 1e-3, FP32 streams, rel KKT 1e-4")
+                "one 128x128 pair, 5 Gaussian blobs + floor 1e-3")
+    if name == "pair128noise":
+        return ([workloads.pair_medium("noise")], 1e-4, hot.HOT_FP32_STREAM,
+                "one 128x128 pair, U(0,1) noise")
     if name == "pair512":
         return ([workloads.pair_large()], 1e-4, hot.HOT_FP32_STREAM,
-                "one 512x512 pair, 1-8 Gaussian blobs + Cauchy blob, floor 1e-6, FP32 streams, "
-                "rel KKT 1e-4")
+                "one 512x512 pair, 1-8 Gaussian blobs + Cauchy blob, floor 1e-6")
     if name == "small":
         return ([workloads.pair_small()], 1e-6, hot.HOT_FP64,
-                "one 32x32 pair, 3 Gaussian blobs + floor 1e-3, FP64, rel KKT 1e-6")
+                "one 32x32 pair, 3 Gaussian blobs + floor 1e-3")
     raise SystemExit(f"unknown workload {name}")
+
+
+def describe(base, prec, tol, sigma_update):
+    from paper_2408_00598_amd import hot
+    p = "FP32 streams + FP64 reductions" if prec == hot.HOT_FP32_STREAM else "FP64"
+    return f"{base}, {p}, rel KKT {tol:g}" + (", sigma re-balanced at restarts"
+                                              if sigma_update else "")
 
 
 def run_serving(args):
@@ -244,7 +254,12 @@ def main():
                     help="serving: seconds to keep draining after the last arrival")
     ap.add_argument("--pool", type=int, default=8, help="serving distinct pairs per side")
     ap.add_argument("--sigma-update", action="store_true",
-                    help="serving: requests re-balance sigma at restarts (HOT_FLAG_SIGMA_UPDATE)")
+                    help="solves re-balance sigma at restarts (HOT_FLAG_SIGMA_UPDATE)")
+    ap.add_argument("--prec", choices=("fp32", "fp64"), default=None,
+                    help="override the workload's precision (fp32: FP32 streams + FP64 "
+                         "reductions; fp64: FP64 throughout)")
+    ap.add_argument("--tol", type=float, default=None,
+                    help="override the workload's relative KKT tolerance")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) 5 times, for scaling "
                          "hardware byte counters")
@@ -260,12 +275,19 @@ def main():
     import torch
     from paper_2408_00598_amd import hot
 
-    pairs, tol, prec, desc = make_workload(args.workload, args.pairs)
+    pairs, tol, prec, base = make_workload(args.workload, args.pairs)
+    default_run = args.prec is None and args.tol is None and not args.sigma_update
+    if args.prec is not None:
+        prec = hot.HOT_FP32_STREAM if args.prec == "fp32" else hot.HOT_FP64
+    if args.tol is not None:
+        tol = args.tol
+    desc = describe(base, prec, tol, args.sigma_update)
     dev = torch.device("cuda:0")
     dpairs = [(torch.tensor(a, device=dev), torch.tensor(b, device=dev)) for a, b in pairs]
     torch.cuda.synchronize()
     ctx = hot.Context(0)
-    kw = dict(tol=tol, max_iter=1000000, prec=prec)
+    flags = hot.HOT_FLAG_RESTART | (hot.HOT_FLAG_SIGMA_UPDATE if args.sigma_update else 0)
+    kw = dict(tol=tol, max_iter=1000000, prec=prec, flags=flags)
 
     plan_stats = []
 
@@ -313,7 +335,8 @@ def main():
     prof = ctx.profile()
     ctx.set_profiling(False)
     achieved = prof["slab_bytes"] / prof["slab_seconds"] / 1e9 if prof["slab_seconds"] else 0.0
-    traffic = measured_traffic(args.workload, launch_key(tuned))
+    # (the committed counter summaries cover the workloads' own precision and tolerance)
+    traffic = measured_traffic(args.workload, launch_key(tuned)) if default_run else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS,
                 "traffic": traffic,  # GB per launch (rocprofv3 FETCH/WRITE, copy-calibrated)
@@ -353,7 +376,7 @@ def main():
             ts = []
             for a, b in lst[:2]:
                 t1 = time.perf_counter()
-                ctx.solve(a, b, tol=tol, max_iter=1000000, prec=hot.HOT_FP64)
+                ctx.solve(a, b, tol=tol, max_iter=1000000, prec=hot.HOT_FP64, flags=flags)
                 ts.append(time.perf_counter() - t1)
             est += np.mean(ts) * len(lst)
             sample.append(f"{shp[0]}: {np.mean(ts)*1e3:.1f} ms")
