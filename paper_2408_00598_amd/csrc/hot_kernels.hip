@@ -531,7 +531,8 @@ template <int FROM_R>
 __device__ void solve_alpha_tile(const PairGeo& G, int tile, const double* rowsum,
                                  const double* arr, const double* vec, double* ab,
                                  const SolveScalars& S) {
-  __shared__ double T1[32][33], T2[32][33], Y[32][33];
+  // T1 holds R1 (or the F1 row sums) and then, in place, y1 of the tile
+  __shared__ double T1[32][33], T2[32][33];
   __shared__ double s_rs[32], s_a[32], s_cn[32], s_qt[32], s_p3[32], s_cm[32];
   const int m = G.m, n = G.n;
   const double dm = (double)m, dn = (double)n;
@@ -577,14 +578,14 @@ __device__ void solve_alpha_tile(const PairGeo& G, int tile, const double* rowsu
       const double rh = r1 - s_a[jj] / dm + s_p3[kk] / dn;
       const double y = (rh + s_qt[kk] + s_rs[jj] / dn) / (dm + dn);
       ab[F1.aboff + (int64_t)j * 2 * m + k] = y;
-      Y[jj][kk] = y;
+      T1[jj][kk] = y;  // (this thread alone read T1[jj][kk] above)
     }
   }
   __syncthreads();
   for (int e = t; e < 1024; e += kWG) {
     const int kk = e >> 5, jj = e & 31;
     const int j = j0 + jj, k = k0 + kk;
-    if (j < n && k < m) ab[F2.aboff + (int64_t)k * 2 * n + j] = -Y[jj][kk];
+    if (j < n && k < m) ab[F2.aboff + (int64_t)k * 2 * n + j] = -T1[jj][kk];
   }
 }
 
