@@ -145,7 +145,7 @@ hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
  * times `iters` fixed iterations (slab pass, reduce and solve, in captured
  * graphs, hipEvents around the run), each pass streaming the state, a (zero)
  * Halpern anchor and the new state as every pass after the first restart
- * does, under each candidate workgroup size (2^13 ..
+ * does, under each candidate workgroup size (2^11 ..
  * 2^17 flow elements per workgroup), row unroll (1, 2) and 16-byte vectors
  * per lane per slab row (2, 4), and keeps the fastest in ctx for launches of the
  * same precision, size class (floor(log2) of the total flow elements) and

@@ -80,7 +80,7 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
     cands.push_back({t.item_elems_for(total, count, fp32), t.unroll_for(total, count, fp32),
                      t.vec_per_lane_for(total, count, fp32)});
   }
-  for (int64_t e = 8192; e <= 131072; e *= 2)
+  for (int64_t e = 2048; e <= 131072; e *= 2)
     for (int u = 1; u <= 2; ++u)
       for (int v = 2; v <= 4; v += 2) cands.push_back({e, u, v});
   for (size_t c = 0; c < cands.size() && status == HOT_OK; ++c) {
