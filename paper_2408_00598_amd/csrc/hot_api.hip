@@ -185,8 +185,12 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
           lay.sitems.push_back(SmallItem{(int32_t)p, fam, s, std::min(4, F.nslab - s)});
     }
     g.nitem = (int32_t)lay.items.size() - g.item0;
-    g.nb1 = (n + 3) / 4;                // reduce row blocks: rows j = 4b..4b+3 of F1,
-    g.nblk = g.nb1 + (m + 3) / 4;       // then rows k = 4b..4b+3 of F2
+    // reduce row blocks: rows j = 4b..4b+3 of F1 (row j alone when F1 is
+    // wide), then the rows k of F2 likewise
+    g.f[0].wide = m >= kWideSide ? 1 : 0;
+    g.f[1].wide = n >= kWideSide ? 1 : 0;
+    g.nb1 = g.f[0].wide ? n : (n + 3) / 4;
+    g.nblk = g.nb1 + (g.f[1].wide ? m : (m + 3) / 4);
     g.ns1 = (m + 63) / 64;              // reduce strips over the columns k of rs1
     g.ns2 = (n + 63) / 64;              // reduce strips over the columns j of rs2
     g.nsblk = (m + n + 3) / 4;          // solve row blocks: slabs 4b..4b+3

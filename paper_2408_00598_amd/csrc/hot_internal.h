@@ -26,6 +26,8 @@ constexpr int kWG = 256;        // threads per workgroup of every kernel
 constexpr int kKI = 8;          // per-item KKT partials written by the slab pass
 constexpr int kKP = 12;         // per-block partials written by the pair reduce
 constexpr int kMaxSide = 1024;  // largest supported m or n
+constexpr int kWideSide = 256;  // slab side from which the pair reduce gives a
+                                // slab a whole workgroup instead of one wave
 
 enum Mode : int32_t {
   MODE_IDLE = 0,
@@ -57,7 +59,8 @@ struct FamGeo {
   int32_t rpc;     // rows per chunk
   int32_t lrs;     // log2(lanes per row)
   int32_t vpl;     // 16-byte vectors per lane per row
-  int32_t pad;
+  int32_t wide;    // 1: the pair reduce gives each slab a whole workgroup (its
+                   // columns split over the four waves); 0: one wave per slab
   int64_t soff;    // element offset of slab 0 in each state buffer
   int64_t aboff;   // double offset of slab 0's alpha; beta follows (2L per slab)
   int64_t rsoff;   // double offset of the row sums (L per slab)
@@ -81,7 +84,8 @@ struct PairGeo {
   int32_t m, n;
   int32_t item0, nitem;  // slab-pass items of this pair
   int32_t blk0, nblk;    // reduce row blocks of this pair: nb1 of F1 rows j, then F2 rows k
-                         // (4 rows each; one KKT / solve-sum slot per block)
+                         // (4 rows each, or 1 for a wide family; one KKT / solve-sum
+                         // slot per block)
   int32_t ns1, ns2;      // reduce strip blocks: 64 columns k of rs1 / 64 columns j of rs2
   int32_t sblk0, nsblk;  // solve row blocks (4 slabs each)
   int32_t ntj, ntk;      // solve tiles: 32 j x 32 k each

@@ -33,6 +33,9 @@ void launch_slab_pass(const LaunchArgs& a, int par, hipStream_t st);
 //           R3^T and the total of row k of the F2 row sums;
 //   kind 1, strip s: u1[k] = sum_j rs1[j][k] for 64 columns k (lane per column);
 //   kind 2, strip s: u2[j] = sum_k rs2[k][j] for 64 columns j.
+// A family with slab side >= kWideSide ("wide") instead gives each row a
+// whole block (row j = b or k = b, the 256 threads over its columns), so a
+// large pair spreads its column-partial sums over four times the waves.
 // Column sums of a slab arrive as per-chunk partials; they are added with
 // four independent accumulators (fixed order) so the loads overlap.
 // R1 itself is never stored: the solve reads it straight from the two
@@ -73,6 +76,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     double* __restrict__ vec, unsigned long long* __restrict__ bytes_ctr, int elem) {
   __shared__ double wred[4][kKP];
   __shared__ double strip[4][64];
+  __shared__ double blk_red[4];
   const PBlock pbk = blocks[blockIdx.x];
   const PairCtl* cp = ctl + pbk.pair;
   if (cp->status != ST_RUNNING) return;
@@ -132,26 +136,35 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   }
   const bool f1 = pbk.kind == 0;
   const int slot = f1 ? b : G.nb1 + b;
+  // narrow family: wave w takes slab 4b + w, its lanes the columns; wide
+  // family (large slabs): the block takes slab b, its 256 threads the columns
+  const bool wide = (f1 ? F1.wide : F2.wide) != 0;
+  const int r = wide ? b : 4 * b + wave;  // row j (F1 block) or k (F2 block)
+  const int tid = wide ? (int)threadIdx.x : lane;
+  const int nthr = wide ? kWG : 64;
+  const bool lead = tid == 0;             // writes the slab's totals
+  // a slab total: over the wave, or over the block for a wide family (every
+  // thread of the block calls it then)
+  auto slab_sum = [&](double v) { return wide ? block_sum(v, blk_red) : wave_sum(v); };
   const double isg = 1.0 / cp->sigma;
   const double* mu1T = arr + arr_mu1T(G);
   const double* mu2 = arr + arr_mu2(G);
-  const int r = 4 * b + wave;  // row j (F1 block) or k (F2 block)
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;  // (sum a_j, sum PR3, sum Sp / D) partials
   if (f1 && r < n) {
     const int j = r;
     double* R2 = arr + arr_R2(G);
     double sr2 = 0.0, t1 = 0.0;
     const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
-    for (int i = lane; i < m; i += 64) {
+    for (int i = tid; i < m; i += nthr) {
       const double cs = chunk_sum(cpj + i, F1.nchunk, m);
       const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - fam_cr(ab, F1, i));
       R2[(int64_t)j * m + i] = r2;
       sr2 += r2;
       t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
     }
-    sr2 = wave_sum(sr2);
-    t1 = wave_sum(t1);
-    if (lane == 0) {
+    sr2 = slab_sum(sr2);
+    t1 = slab_sum(t1);
+    if (lead) {
       vec[vec_a(G) + j] = sr2;
       vec[vec_tot1(G) + j] = t1;
     }
@@ -161,7 +174,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     double* R3T = arr + arr_R3T(G);
     double s3 = 0.0, t2 = 0.0;
     const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
-    for (int l = lane; l < n; l += 64) {
+    for (int l = tid; l < n; l += nthr) {
       double r3 = 0.0;
       if (!(k == m - 1 && l == n - 1)) {
         const double cs = chunk_sum(cpk + l, F2.nchunk, n);
@@ -171,15 +184,16 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       s3 += r3;
       t2 += rowsum[F2.rsoff + (int64_t)k * n + l];  // row k of the F2 row sums
     }
-    s3 = wave_sum(s3);
-    t2 = wave_sum(t2);
-    if (lane == 0) {
+    s3 = slab_sum(s3);
+    t2 = slab_sum(t2);
+    if (lead) {
       vec[vec_PR3(G) + k] = s3;
       vec[vec_tot2(G) + k] = t2;
     }
     p1 = s3;
     p2 = ((t2 - fam_cc(ab, F2)) + s3) * dinv(m, k);
   }
+  if (wide && wave != 0) p0 = p1 = p2 = 0.0;  // (every wave holds the slab totals)
   if (lane == 0) {
     wred[wave][0] = p0;
     wred[wave][1] = p1;
@@ -189,15 +203,15 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   if (threadIdx.x < 3)
     vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
   const bool su = (cp->flags & 0x10) != 0;
-  // (alpha, beta) of this wave's slab and their stored copy from the last restart
+  // (alpha, beta) of this block's slab and their stored copy from the last restart
   const FamGeo& FS = f1 ? F1 : F2;
   const int LS = f1 ? m : n;
   const bool has_slab = f1 ? r < n : r < m;
   const int64_t aoff = FS.aboff + (int64_t)r * 2 * LS;
   if (mode == MODE_RESTART && su && has_slab) {
     // sigma re-balancing: keep y_bar of this restart (alpha, beta, their sums)
-    for (int q = lane; q < 2 * LS; q += 64) abY[aoff + q] = ab[aoff + q];
-    if (lane < 2) abY[FS.sumoff + 2 * (int64_t)r + lane] = ab[FS.sumoff + 2 * (int64_t)r + lane];
+    for (int q = tid; q < 2 * LS; q += nthr) abY[aoff + q] = ab[aoff + q];
+    if (tid < 2) abY[FS.sumoff + 2 * (int64_t)r + tid] = ab[FS.sumoff + 2 * (int64_t)r + tid];
   }
   if (mode != MODE_CHECK) return;
 
@@ -213,7 +227,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     // ||A^T (y_bar - Y)||^2 over this slab: A^T y is alpha_p + beta_q on it,
     // so the sum over the L x L slab is L sum da^2 + L sum db^2 + 2 sum da sum db
     double a2 = 0.0, b2 = 0.0, sa_ = 0.0, sb_ = 0.0;
-    for (int q = lane; q < LS; q += 64) {
+    for (int q = tid; q < LS; q += nthr) {
       const double da = ab[aoff + q] - abY[aoff + q];
       const double db = ab[aoff + LS + q] - abY[aoff + LS + q];
       a2 += da * da;
@@ -221,11 +235,11 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       sa_ += da;
       sb_ += db;
     }
-    a2 = wave_sum(a2);
-    b2 = wave_sum(b2);
-    sa_ = wave_sum(sa_);
-    sb_ = wave_sum(sb_);
-    if (lane == 0) part[KP_DY] = (double)LS * (a2 + b2) + 2.0 * sa_ * sb_;
+    a2 = slab_sum(a2);
+    b2 = slab_sum(b2);
+    sa_ = slab_sum(sa_);
+    sb_ = slab_sum(sb_);
+    if (lead) part[KP_DY] = (double)LS * (a2 + b2) + 2.0 * sa_ * sb_;
   }
   // primal residual A xbar - b, xbar = sigma (s - g): the sums of s^k are the
   // previous pass's sums; the sums of g over a slab row / column follow from
@@ -237,7 +251,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const double* al = ab + F1.aboff + (int64_t)j * 2 * m;
     const double* be = al + m;
     const double sa = ab[F1.sumoff + 2 * (int64_t)j], sb = ab[F1.sumoff + 2 * (int64_t)j + 1];
-    for (int kk = lane; kk < m; kk += 64) {
+    for (int kk = tid; kk < m; kk += nthr) {
       // row kk of F1^(j) and row j of F2^(kk) share the conservation row (j,kk)
       const double* al2 = ab + F2.aboff + (int64_t)kk * 2 * n;
       const double sb2 = ab[F2.sumoff + 2 * (int64_t)kk + 1];
@@ -249,7 +263,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       prim += rr * rr;
     }
     const double* cpj = colpart_prev + F1.cpoff + (int64_t)j * F1.nchunk * m;
-    for (int i = lane; i < m; i += 64) {
+    for (int i = tid; i < m; i += nthr) {
       const double cs = chunk_sum(cpj + i, F1.nchunk, m);
       const double x = sg * (cs - (fam_cr(ab, F1, i) - sa - m * be[i]));
       const double rr = x - mu1T[(int64_t)j * m + i];
@@ -262,7 +276,7 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     const double* be = al + n;
     const double sa = ab[F2.sumoff + 2 * (int64_t)k];
     const double* cpk = colpart_prev + F2.cpoff + (int64_t)k * F2.nchunk * n;
-    for (int l = lane; l < n; l += 64) {
+    for (int l = tid; l < n; l += nthr) {
       if (k == m - 1 && l == n - 1) continue;
       const double cs = chunk_sum(cpk + l, F2.nchunk, n);
       const double x = sg * (cs - (fam_cr(ab, F2, l) - sa - n * be[l]));
@@ -777,6 +791,7 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
                                                           const double* __restrict__ arr,
                                                           double* __restrict__ vec) {
   __shared__ double wred[4][kKP];
+  __shared__ double blk_red[4];
   const PBlock pbk = blocks[blockIdx.x];
   const PairGeo G = geo[pbk.pair];
   const int m = G.m, n = G.n, b = pbk.blk;
@@ -790,16 +805,21 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
   const double* R1 = arr + arr_R1(G);
   const double* R2 = arr + arr_R2(G);
   const double* R3T = arr + arr_R3T(G);
-  const int r = 4 * b + wave;
+  // the reduce's block shapes: one wave per slab, or the block for a wide family
+  const bool wide = (f1 ? G.f[0].wide : G.f[1].wide) != 0;
+  const int r = wide ? b : 4 * b + wave;
+  const int tid = wide ? (int)threadIdx.x : lane;
+  const int nthr = wide ? kWG : 64;
+  auto slab_sum = [&](double v) { return wide ? block_sum(v, blk_red) : wave_sum(v); };
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
   if (f1 && r < n) {
     const int j = r;
     double s1 = 0.0, s2 = 0.0;
-    for (int kk = lane; kk < m; kk += 64) s1 += R1[(int64_t)j * m + kk];
-    for (int i = lane; i < m; i += 64) s2 += R2[(int64_t)j * m + i];
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    if (lane == 0) {
+    for (int kk = tid; kk < m; kk += nthr) s1 += R1[(int64_t)j * m + kk];
+    for (int i = tid; i < m; i += nthr) s2 += R2[(int64_t)j * m + i];
+    s1 = slab_sum(s1);
+    s2 = slab_sum(s2);
+    if (tid == 0) {
       vec[vec_b1(G) + j] = s1;
       vec[vec_a(G) + j] = s2;
     }
@@ -807,17 +827,18 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
   } else if (!f1 && r < m) {
     const int k = r;
     double s3 = 0.0, c1 = 0.0;
-    for (int l = lane; l < n; l += 64) s3 += R3T[(int64_t)k * n + l];
-    for (int jj = lane; jj < n; jj += 64) c1 += R1[(int64_t)jj * m + k];
-    s3 = wave_sum(s3);
-    c1 = wave_sum(c1);
-    if (lane == 0) {
+    for (int l = tid; l < n; l += nthr) s3 += R3T[(int64_t)k * n + l];
+    for (int jj = tid; jj < n; jj += nthr) c1 += R1[(int64_t)jj * m + k];
+    s3 = slab_sum(s3);
+    c1 = slab_sum(c1);
+    if (tid == 0) {
       vec[vec_PR3(G) + k] = s3;
       vec[vec_Sp(G) + k] = c1 + s3;
     }
     p1 = s3;
     p2 = (c1 + s3) * dinv(m, k);
   }
+  if (wide && wave != 0) p0 = p1 = p2 = 0.0;  // (every wave holds the slab totals)
   if (lane == 0) {
     wred[wave][0] = p0;
     wred[wave][1] = p1;
