@@ -87,9 +87,10 @@ struct PairGeo {
                          // (4 rows each, or 1 for a wide family; one KKT / solve-sum
                          // slot per block)
   int32_t ns1, ns2;      // reduce strip blocks: 64 columns k of rs1 / 64 columns j of rs2
-  int32_t sblk0, nsblk;  // solve row blocks (4 slabs each)
+  int32_t sblk0, nsblk;  // solve row blocks (4 spw slabs each)
   int32_t ntj, ntk;      // solve tiles: 32 j x 32 k each
   int32_t ipb, nb1;      // slab items per reduce row block (KKT reduction); F1 row blocks
+  int32_t spw, pad1;     // slabs per wave of a solve row block (4 spw slabs per block)
   FamGeo f[2];
   int64_t moff;          // double offset of the M-sized arrays (5 of them)
   int64_t voff;          // double offset of the small vectors

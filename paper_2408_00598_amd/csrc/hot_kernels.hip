@@ -426,8 +426,9 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
 //   y3^l = (R3^l + t)/n.
 // The global scalars are rebuilt by one wave from the reduce blocks'
 // partials in a fixed order, so solve blocks need no communication.
-//   kind 0, row block b: wave w writes beta of slab 4b + w (F1 slabs j
-//           first, then F2 slabs k) and the slab's (sum alpha, sum beta);
+//   kind 0, row block b: wave w writes beta of slabs 4(spw b + q) + w,
+//           q < spw (F1 slabs j first, then F2 slabs k) and each slab's
+//           (sum alpha, sum beta);
 //   kind 1, tile (jt, kt): y1 on a 32 x 32 tile of (j, k), written as
 //           alpha of F1^(j) (row j) and, transposed through LDS, as
 //           -alpha of F2^(k) (row k).
@@ -645,7 +646,9 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
   __syncthreads();
   if (s_solve) {
     if (pbk.kind == 0)
-      solve_beta<FROM_R>(G, 4 * pbk.blk + (threadIdx.x >> 6), arr, vec, ab, s_S, threadIdx.x & 63);
+      for (int q = 0; q < G.spw; ++q)  // slabs 4 (spw b + q) + w
+        solve_beta<FROM_R>(G, 4 * (G.spw * pbk.blk + q) + (threadIdx.x >> 6), arr, vec, ab, s_S,
+                           threadIdx.x & 63);
     else
       solve_alpha_tile<FROM_R>(G, pbk.blk, rowsum, arr, vec, ab, s_S);
   }

@@ -54,6 +54,26 @@ def test_fused_and_split_slab_kernels_bitwise(monkeypatch):
             assert torch.equal(t0, t1)
 
 
+def test_solve_slabs_per_wave_bitwise(monkeypatch):
+    """Solve row blocks of one or four slabs per wave compute every slab's
+    beta the same way: identical results (the default picks four for
+    launches with many row blocks)."""
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    pairs = workloads.batch_pairs(8, sides=(16, 40, 72, 130))
+    dp = [(dev(a), dev(b)) for a, b in pairs]
+    ctxs = []
+    for spw in ("1", "4", "3"):
+        monkeypatch.setenv("HOT_SOLVE_SPW", spw)
+        ctxs.append(hot.Context(0))
+    for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
+        rs = [c.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec) for c in ctxs]
+        for other in rs[1:]:
+            for ra, rb in zip(rs[0], other):
+                for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
+                    assert ra[key] == rb[key], (prec, key, ra[key], rb[key])
+
+
 def test_batch_matches_oracle(oracle):
     need_gpu()
     from paper_2408_00598_amd import workloads
