@@ -97,7 +97,7 @@ Tuning default_tuning() {
   t.small_side = 64;
   t.batch_groups = 2;
   t.fuse = 1;
-  t.solve_spw = 0;
+  t.row_group = 0;
   return t;
 }
 
@@ -136,12 +136,14 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   const int64_t item_elems = tune.item_elems_for(total, npairs, fp32);
   int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0, taboff = 0;
   int maxvpl = 1;
-  // a launch with many solve row blocks gives each wave four slabs, so that
-  // fewer blocks repeat the per-pair prologue (256-pair batch: +2%); a few
-  // pairs keep one slab per wave for parallelism (128 x 128 alone: -4% with four)
+  // a launch with many row blocks gives each solve wave four slabs and each
+  // reduce block four slots, so that fewer blocks repeat the per-pair
+  // prologue (256-pair batch: +2% from the solve, +0.5% from the reduce); a
+  // few pairs keep one per block for parallelism (128 x 128 alone: -4% with
+  // four)
   int64_t rows4 = 0;
   for (const auto& sh : shapes) rows4 += (sh.first + sh.second + 3) / 4;
-  const int solve_spw = tune.solve_spw > 0 ? tune.solve_spw : (rows4 > 2048 ? 4 : 1);
+  const int row_group = tune.row_group > 0 ? tune.row_group : (rows4 > 2048 ? 4 : 1);
   for (size_t p = 0; p < shapes.size(); ++p) {
     const int m = shapes[p].first, n = shapes[p].second;
     PairGeo g;
@@ -202,14 +204,18 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
     g.ns2 = (n + 63) / 64;              // reduce strips over the columns j of rs2
     // solve row blocks: slabs 4 spw b .. 4 spw (b + 1) - 1 (the result does
     // not depend on spw)
-    g.spw = solve_spw;
+    g.spw = row_group;
     g.nsblk = (m + n + 4 * g.spw - 1) / (4 * g.spw);
     g.ntj = (n + 31) / 32;              // solve tiles
     g.ntk = (m + 31) / 32;
     g.ipb = (g.nitem + g.nblk - 1) / g.nblk;
     g.blk0 = (int32_t)lay.blocks.size();
-    for (int b = 0; b < g.nb1; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 0, 0});
-    for (int b = 0; b < g.nblk - g.nb1; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 3, 0});
+    g.rq = row_group;  // (the grouping of slots into blocks does not change the result)
+    const int rq1 = g.f[0].wide ? 1 : g.rq, rq2 = g.f[1].wide ? 1 : g.rq;
+    for (int b = 0; b < (g.nb1 + rq1 - 1) / rq1; ++b)
+      lay.blocks.push_back(PBlock{(int32_t)p, b, 0, 0});
+    for (int b = 0; b < (g.nblk - g.nb1 + rq2 - 1) / rq2; ++b)
+      lay.blocks.push_back(PBlock{(int32_t)p, b, 3, 0});
     for (int b = 0; b < g.ns1; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 1, 0});
     for (int b = 0; b < g.ns2; ++b) lay.blocks.push_back(PBlock{(int32_t)p, b, 2, 0});
     g.sblk0 = (int32_t)lay.sblocks.size();
@@ -927,8 +933,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.min_items = std::max<int64_t>(1, std::atoll(e));
   e = std::getenv("HOT_SMALL_SIDE");
   if (e) c->tune.small_side = std::max(0, std::atoi(e));
-  e = std::getenv("HOT_SOLVE_SPW");
-  if (e) c->tune.solve_spw = std::max(0, std::min(16, std::atoi(e)));
+  e = std::getenv("HOT_ROW_GROUP");
+  if (e) c->tune.row_group = std::max(0, std::min(16, std::atoi(e)));
   e = std::getenv("HOT_FUSE");
   if (e) c->tune.fuse = std::atoi(e) != 0;
   e = std::getenv("HOT_BATCH_GROUPS");

@@ -83,14 +83,15 @@ __host__ __device__ inline double fam_cc(const double* ab, const FamGeo& F) {
 struct PairGeo {
   int32_t m, n;
   int32_t item0, nitem;  // slab-pass items of this pair
-  int32_t blk0, nblk;    // reduce row blocks of this pair: nb1 of F1 rows j, then F2 rows k
+  int32_t blk0, nblk;    // reduce slots of this pair: nb1 of F1 rows j, then F2 rows k
                          // (4 rows each, or 1 for a wide family; one KKT / solve-sum
-                         // slot per block)
+                         // partial each); a reduce row block takes rq slots
   int32_t ns1, ns2;      // reduce strip blocks: 64 columns k of rs1 / 64 columns j of rs2
   int32_t sblk0, nsblk;  // solve row blocks (4 spw slabs each)
   int32_t ntj, ntk;      // solve tiles: 32 j x 32 k each
   int32_t ipb, nb1;      // slab items per reduce row block (KKT reduction); F1 row blocks
-  int32_t spw, pad1;     // slabs per wave of a solve row block (4 spw slabs per block)
+  int32_t spw, rq;       // slabs per wave of a solve row block (4 spw slabs per block);
+                         // reduce slots per reduce row block of a narrow family
   FamGeo f[2];
   int64_t moff;          // double offset of the M-sized arrays (5 of them)
   int64_t voff;          // double offset of the small vectors

@@ -135,166 +135,174 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     return;
   }
   const bool f1 = pbk.kind == 0;
-  const int slot = f1 ? b : G.nb1 + b;
-  // narrow family: wave w takes slab 4b + w, its lanes the columns; wide
-  // family (large slabs): the block takes slab b, its 256 threads the columns
+  // narrow family: slot q holds rows 4q..4q+3 (wave w takes row 4q + w, its
+  // lanes the columns) and a block takes rq consecutive slots; wide family
+  // (large slabs): slot q is row q alone, its block's 256 threads the columns
   const bool wide = (f1 ? F1.wide : F2.wide) != 0;
-  const int r = wide ? b : 4 * b + wave;  // row j (F1 block) or k (F2 block)
-  const int tid = wide ? (int)threadIdx.x : lane;
-  const int nthr = wide ? kWG : 64;
-  const bool lead = tid == 0;             // writes the slab's totals
-  // a slab total: over the wave, or over the block for a wide family (every
-  // thread of the block calls it then)
-  auto slab_sum = [&](double v) { return wide ? block_sum(v, blk_red) : wave_sum(v); };
-  const double isg = 1.0 / cp->sigma;
-  const double* mu1T = arr + arr_mu1T(G);
-  const double* mu2 = arr + arr_mu2(G);
-  double p0 = 0.0, p1 = 0.0, p2 = 0.0;  // (sum a_j, sum PR3, sum Sp / D) partials
-  if (f1 && r < n) {
-    const int j = r;
-    double* R2 = arr + arr_R2(G);
-    double sr2 = 0.0, t1 = 0.0;
-    const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
-    for (int i = tid; i < m; i += nthr) {
-      const double cs = chunk_sum(cpj + i, F1.nchunk, m);
-      const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - fam_cr(ab, F1, i));
-      R2[(int64_t)j * m + i] = r2;
-      sr2 += r2;
-      t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
-    }
-    sr2 = slab_sum(sr2);
-    t1 = slab_sum(t1);
-    if (lead) {
-      vec[vec_a(G) + j] = sr2;
-      vec[vec_tot1(G) + j] = t1;
-    }
-    p0 = sr2;
-  } else if (!f1 && r < m) {
-    const int k = r;
-    double* R3T = arr + arr_R3T(G);
-    double s3 = 0.0, t2 = 0.0;
-    const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
-    for (int l = tid; l < n; l += nthr) {
-      double r3 = 0.0;
-      if (!(k == m - 1 && l == n - 1)) {
-        const double cs = chunk_sum(cpk + l, F2.nchunk, n);
-        r3 = mu2[(int64_t)k * n + l] * isg - (cs - fam_cr(ab, F2, l));
+  const int nq = wide ? 1 : G.rq;
+  const int nslot = f1 ? G.nb1 : G.nblk - G.nb1;
+  for (int qd = 0; qd < nq; ++qd) {
+    const int sq = nq * b + qd;  // slot within the family
+    if (sq >= nslot) break;
+    if (qd > 0) __syncthreads();  // the previous slot's wred has been read
+    const int slot = f1 ? sq : G.nb1 + sq;
+    const int r = wide ? sq : 4 * sq + wave;  // row j (F1 block) or k (F2 block)
+    const int tid = wide ? (int)threadIdx.x : lane;
+    const int nthr = wide ? kWG : 64;
+    const bool lead = tid == 0;             // writes the slab's totals
+    // a slab total: over the wave, or over the block for a wide family (every
+    // thread of the block calls it then)
+    auto slab_sum = [&](double v) { return wide ? block_sum(v, blk_red) : wave_sum(v); };
+    const double isg = 1.0 / cp->sigma;
+    const double* mu1T = arr + arr_mu1T(G);
+    const double* mu2 = arr + arr_mu2(G);
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;  // (sum a_j, sum PR3, sum Sp / D) partials
+    if (f1 && r < n) {
+      const int j = r;
+      double* R2 = arr + arr_R2(G);
+      double sr2 = 0.0, t1 = 0.0;
+      const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
+      for (int i = tid; i < m; i += nthr) {
+        const double cs = chunk_sum(cpj + i, F1.nchunk, m);
+        const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - fam_cr(ab, F1, i));
+        R2[(int64_t)j * m + i] = r2;
+        sr2 += r2;
+        t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
       }
-      R3T[(int64_t)k * n + l] = r3;
-      s3 += r3;
-      t2 += rowsum[F2.rsoff + (int64_t)k * n + l];  // row k of the F2 row sums
+      sr2 = slab_sum(sr2);
+      t1 = slab_sum(t1);
+      if (lead) {
+        vec[vec_a(G) + j] = sr2;
+        vec[vec_tot1(G) + j] = t1;
+      }
+      p0 = sr2;
+    } else if (!f1 && r < m) {
+      const int k = r;
+      double* R3T = arr + arr_R3T(G);
+      double s3 = 0.0, t2 = 0.0;
+      const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
+      for (int l = tid; l < n; l += nthr) {
+        double r3 = 0.0;
+        if (!(k == m - 1 && l == n - 1)) {
+          const double cs = chunk_sum(cpk + l, F2.nchunk, n);
+          r3 = mu2[(int64_t)k * n + l] * isg - (cs - fam_cr(ab, F2, l));
+        }
+        R3T[(int64_t)k * n + l] = r3;
+        s3 += r3;
+        t2 += rowsum[F2.rsoff + (int64_t)k * n + l];  // row k of the F2 row sums
+      }
+      s3 = slab_sum(s3);
+      t2 = slab_sum(t2);
+      if (lead) {
+        vec[vec_PR3(G) + k] = s3;
+        vec[vec_tot2(G) + k] = t2;
+      }
+      p1 = s3;
+      p2 = ((t2 - fam_cc(ab, F2)) + s3) * dinv(m, k);
     }
-    s3 = slab_sum(s3);
-    t2 = slab_sum(t2);
-    if (lead) {
-      vec[vec_PR3(G) + k] = s3;
-      vec[vec_tot2(G) + k] = t2;
+    if (wide && wave != 0) p0 = p1 = p2 = 0.0;  // (every wave holds the slab totals)
+    if (lane == 0) {
+      wred[wave][0] = p0;
+      wred[wave][1] = p1;
+      wred[wave][2] = p2;
     }
-    p1 = s3;
-    p2 = ((t2 - fam_cc(ab, F2)) + s3) * dinv(m, k);
-  }
-  if (wide && wave != 0) p0 = p1 = p2 = 0.0;  // (every wave holds the slab totals)
-  if (lane == 0) {
-    wred[wave][0] = p0;
-    wred[wave][1] = p1;
-    wred[wave][2] = p2;
-  }
-  __syncthreads();
-  if (threadIdx.x < 3)
-    vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
-  const bool su = (cp->flags & 0x10) != 0;
-  // (alpha, beta) of this block's slab and their stored copy from the last restart
-  const FamGeo& FS = f1 ? F1 : F2;
-  const int LS = f1 ? m : n;
-  const bool has_slab = f1 ? r < n : r < m;
-  const int64_t aoff = FS.aboff + (int64_t)r * 2 * LS;
-  if (mode == MODE_RESTART && su && has_slab) {
-    // sigma re-balancing: keep y_bar of this restart (alpha, beta, their sums)
-    for (int q = tid; q < 2 * LS; q += nthr) abY[aoff + q] = ab[aoff + q];
-    if (tid < 2) abY[FS.sumoff + 2 * (int64_t)r + tid] = ab[FS.sumoff + 2 * (int64_t)r + tid];
-  }
-  if (mode != MODE_CHECK) return;
+    __syncthreads();
+    if (threadIdx.x < 3)
+      vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
+    const bool su = (cp->flags & 0x10) != 0;
+    // (alpha, beta) of this block's slab and their stored copy from the last restart
+    const FamGeo& FS = f1 ? F1 : F2;
+    const int LS = f1 ? m : n;
+    const bool has_slab = f1 ? r < n : r < m;
+    const int64_t aoff = FS.aboff + (int64_t)r * 2 * LS;
+    if (mode == MODE_RESTART && su && has_slab) {
+      // sigma re-balancing: keep y_bar of this restart (alpha, beta, their sums)
+      for (int q = tid; q < 2 * LS; q += nthr) abY[aoff + q] = ab[aoff + q];
+      if (tid < 2) abY[FS.sumoff + 2 * (int64_t)r + tid] = ab[FS.sumoff + 2 * (int64_t)r + tid];
+    }
+    if (mode != MODE_CHECK) continue;
 
-  // ---- check pass: KKT partials of w_bar^k -------------------------------
-  double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  {
-    const int i0 = G.item0 + slot * G.ipb;
-    const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
-    for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
-      for (int q = 0; q <= KI_DX; ++q) part[q] += kitem[(int64_t)it * kKI + q];
-  }
-  if (su && has_slab) {
-    // ||A^T (y_bar - Y)||^2 over this slab: A^T y is alpha_p + beta_q on it,
-    // so the sum over the L x L slab is L sum da^2 + L sum db^2 + 2 sum da sum db
-    double a2 = 0.0, b2 = 0.0, sa_ = 0.0, sb_ = 0.0;
-    for (int q = tid; q < LS; q += nthr) {
-      const double da = ab[aoff + q] - abY[aoff + q];
-      const double db = ab[aoff + LS + q] - abY[aoff + LS + q];
-      a2 += da * da;
-      b2 += db * db;
-      sa_ += da;
-      sb_ += db;
+    // ---- check pass: KKT partials of w_bar^k -------------------------------
+    double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    {
+      const int i0 = G.item0 + slot * G.ipb;
+      const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
+      for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
+        for (int q = 0; q <= KI_DX; ++q) part[q] += kitem[(int64_t)it * kKI + q];
     }
-    a2 = slab_sum(a2);
-    b2 = slab_sum(b2);
-    sa_ = slab_sum(sa_);
-    sb_ = slab_sum(sb_);
-    if (lead) part[KP_DY] = (double)LS * (a2 + b2) + 2.0 * sa_ * sb_;
-  }
-  // primal residual A xbar - b, xbar = sigma (s - g): the sums of s^k are the
-  // previous pass's sums; the sums of g over a slab row / column follow from
-  // alpha, beta and their per-slab totals.
-  const double sg = cp->sigma;
-  double prim = 0.0, by = 0.0;
-  if (f1 && r < n) {
-    const int j = r;
-    const double* al = ab + F1.aboff + (int64_t)j * 2 * m;
-    const double* be = al + m;
-    const double sa = ab[F1.sumoff + 2 * (int64_t)j], sb = ab[F1.sumoff + 2 * (int64_t)j + 1];
-    for (int kk = tid; kk < m; kk += nthr) {
-      // row kk of F1^(j) and row j of F2^(kk) share the conservation row (j,kk)
-      const double* al2 = ab + F2.aboff + (int64_t)kk * 2 * n;
-      const double sb2 = ab[F2.sumoff + 2 * (int64_t)kk + 1];
-      const double x1 = sg * (rowsum_prev[F1.rsoff + (int64_t)j * m + kk] -
-                              (fam_cr(ab, F1, kk) - m * al[kk] - sb));
-      const double x2 = sg * (rowsum_prev[F2.rsoff + (int64_t)kk * n + j] -
-                              (fam_cr(ab, F2, j) - n * al2[j] - sb2));
-      const double rr = x1 - x2;
-      prim += rr * rr;
+    if (su && has_slab) {
+      // ||A^T (y_bar - Y)||^2 over this slab: A^T y is alpha_p + beta_q on it,
+      // so the sum over the L x L slab is L sum da^2 + L sum db^2 + 2 sum da sum db
+      double a2 = 0.0, b2 = 0.0, sa_ = 0.0, sb_ = 0.0;
+      for (int q = tid; q < LS; q += nthr) {
+        const double da = ab[aoff + q] - abY[aoff + q];
+        const double db = ab[aoff + LS + q] - abY[aoff + LS + q];
+        a2 += da * da;
+        b2 += db * db;
+        sa_ += da;
+        sb_ += db;
+      }
+      a2 = slab_sum(a2);
+      b2 = slab_sum(b2);
+      sa_ = slab_sum(sa_);
+      sb_ = slab_sum(sb_);
+      if (lead) part[KP_DY] = (double)LS * (a2 + b2) + 2.0 * sa_ * sb_;
     }
-    const double* cpj = colpart_prev + F1.cpoff + (int64_t)j * F1.nchunk * m;
-    for (int i = tid; i < m; i += nthr) {
-      const double cs = chunk_sum(cpj + i, F1.nchunk, m);
-      const double x = sg * (cs - (fam_cr(ab, F1, i) - sa - m * be[i]));
-      const double rr = x - mu1T[(int64_t)j * m + i];
-      prim += rr * rr;
-      by += mu1T[(int64_t)j * m + i] * be[i];
+    // primal residual A xbar - b, xbar = sigma (s - g): the sums of s^k are the
+    // previous pass's sums; the sums of g over a slab row / column follow from
+    // alpha, beta and their per-slab totals.
+    const double sg = cp->sigma;
+    double prim = 0.0, by = 0.0;
+    if (f1 && r < n) {
+      const int j = r;
+      const double* al = ab + F1.aboff + (int64_t)j * 2 * m;
+      const double* be = al + m;
+      const double sa = ab[F1.sumoff + 2 * (int64_t)j], sb = ab[F1.sumoff + 2 * (int64_t)j + 1];
+      for (int kk = tid; kk < m; kk += nthr) {
+        // row kk of F1^(j) and row j of F2^(kk) share the conservation row (j,kk)
+        const double* al2 = ab + F2.aboff + (int64_t)kk * 2 * n;
+        const double sb2 = ab[F2.sumoff + 2 * (int64_t)kk + 1];
+        const double x1 = sg * (rowsum_prev[F1.rsoff + (int64_t)j * m + kk] -
+                                (fam_cr(ab, F1, kk) - m * al[kk] - sb));
+        const double x2 = sg * (rowsum_prev[F2.rsoff + (int64_t)kk * n + j] -
+                                (fam_cr(ab, F2, j) - n * al2[j] - sb2));
+        const double rr = x1 - x2;
+        prim += rr * rr;
+      }
+      const double* cpj = colpart_prev + F1.cpoff + (int64_t)j * F1.nchunk * m;
+      for (int i = tid; i < m; i += nthr) {
+        const double cs = chunk_sum(cpj + i, F1.nchunk, m);
+        const double x = sg * (cs - (fam_cr(ab, F1, i) - sa - m * be[i]));
+        const double rr = x - mu1T[(int64_t)j * m + i];
+        prim += rr * rr;
+        by += mu1T[(int64_t)j * m + i] * be[i];
+      }
+    } else if (!f1 && r < m) {
+      const int k = r;
+      const double* al = ab + F2.aboff + (int64_t)k * 2 * n;
+      const double* be = al + n;
+      const double sa = ab[F2.sumoff + 2 * (int64_t)k];
+      const double* cpk = colpart_prev + F2.cpoff + (int64_t)k * F2.nchunk * n;
+      for (int l = tid; l < n; l += nthr) {
+        if (k == m - 1 && l == n - 1) continue;
+        const double cs = chunk_sum(cpk + l, F2.nchunk, n);
+        const double x = sg * (cs - (fam_cr(ab, F2, l) - sa - n * be[l]));
+        const double rr = x - mu2[(int64_t)k * n + l];
+        prim += rr * rr;
+        by += mu2[(int64_t)k * n + l] * be[l];
+      }
     }
-  } else if (!f1 && r < m) {
-    const int k = r;
-    const double* al = ab + F2.aboff + (int64_t)k * 2 * n;
-    const double* be = al + n;
-    const double sa = ab[F2.sumoff + 2 * (int64_t)k];
-    const double* cpk = colpart_prev + F2.cpoff + (int64_t)k * F2.nchunk * n;
-    for (int l = tid; l < n; l += nthr) {
-      if (k == m - 1 && l == n - 1) continue;
-      const double cs = chunk_sum(cpk + l, F2.nchunk, n);
-      const double x = sg * (cs - (fam_cr(ab, F2, l) - sa - n * be[l]));
-      const double rr = x - mu2[(int64_t)k * n + l];
-      prim += rr * rr;
-      by += mu2[(int64_t)k * n + l] * be[l];
+    part[KP_PRIM] = prim;
+    part[KP_BY] = by;
+    __syncthreads();
+    for (int q = 0; q < kNKP; ++q) {
+      const double v = wave_sum(part[q]);
+      if (lane == 0) wred[wave][q] = v;
     }
+    __syncthreads();
+    if (threadIdx.x < kNKP)
+      vec[vec_kpart(G) + (int64_t)slot * kKP + threadIdx.x] = wave4(wred, threadIdx.x);
   }
-  part[KP_PRIM] = prim;
-  part[KP_BY] = by;
-  __syncthreads();
-  for (int q = 0; q < kNKP; ++q) {
-    const double v = wave_sum(part[q]);
-    if (lane == 0) wred[wave][q] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < kNKP)
-    vec[vec_kpart(G) + (int64_t)slot * kKP + threadIdx.x] = wave4(wred, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -804,52 +812,59 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
     return;
   }
   const bool f1 = pbk.kind == 0;
-  const int slot = f1 ? b : G.nb1 + b;
   const double* R1 = arr + arr_R1(G);
   const double* R2 = arr + arr_R2(G);
   const double* R3T = arr + arr_R3T(G);
   // the reduce's block shapes: one wave per slab, or the block for a wide family
   const bool wide = (f1 ? G.f[0].wide : G.f[1].wide) != 0;
-  const int r = wide ? b : 4 * b + wave;
-  const int tid = wide ? (int)threadIdx.x : lane;
-  const int nthr = wide ? kWG : 64;
-  auto slab_sum = [&](double v) { return wide ? block_sum(v, blk_red) : wave_sum(v); };
-  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  if (f1 && r < n) {
-    const int j = r;
-    double s1 = 0.0, s2 = 0.0;
-    for (int kk = tid; kk < m; kk += nthr) s1 += R1[(int64_t)j * m + kk];
-    for (int i = tid; i < m; i += nthr) s2 += R2[(int64_t)j * m + i];
-    s1 = slab_sum(s1);
-    s2 = slab_sum(s2);
-    if (tid == 0) {
-      vec[vec_b1(G) + j] = s1;
-      vec[vec_a(G) + j] = s2;
+  const int nq = wide ? 1 : G.rq;
+  const int nslot = f1 ? G.nb1 : G.nblk - G.nb1;
+  for (int qd = 0; qd < nq; ++qd) {
+    const int sq = nq * b + qd;  // slot within the family
+    if (sq >= nslot) break;
+    if (qd > 0) __syncthreads();  // the previous slot's wred has been read
+    const int slot = f1 ? sq : G.nb1 + sq;
+    const int r = wide ? sq : 4 * sq + wave;
+    const int tid = wide ? (int)threadIdx.x : lane;
+    const int nthr = wide ? kWG : 64;
+    auto slab_sum = [&](double v) { return wide ? block_sum(v, blk_red) : wave_sum(v); };
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    if (f1 && r < n) {
+      const int j = r;
+      double s1 = 0.0, s2 = 0.0;
+      for (int kk = tid; kk < m; kk += nthr) s1 += R1[(int64_t)j * m + kk];
+      for (int i = tid; i < m; i += nthr) s2 += R2[(int64_t)j * m + i];
+      s1 = slab_sum(s1);
+      s2 = slab_sum(s2);
+      if (tid == 0) {
+        vec[vec_b1(G) + j] = s1;
+        vec[vec_a(G) + j] = s2;
+      }
+      p0 = s2;
+    } else if (!f1 && r < m) {
+      const int k = r;
+      double s3 = 0.0, c1 = 0.0;
+      for (int l = tid; l < n; l += nthr) s3 += R3T[(int64_t)k * n + l];
+      for (int jj = tid; jj < n; jj += nthr) c1 += R1[(int64_t)jj * m + k];
+      s3 = slab_sum(s3);
+      c1 = slab_sum(c1);
+      if (tid == 0) {
+        vec[vec_PR3(G) + k] = s3;
+        vec[vec_Sp(G) + k] = c1 + s3;
+      }
+      p1 = s3;
+      p2 = (c1 + s3) * dinv(m, k);
     }
-    p0 = s2;
-  } else if (!f1 && r < m) {
-    const int k = r;
-    double s3 = 0.0, c1 = 0.0;
-    for (int l = tid; l < n; l += nthr) s3 += R3T[(int64_t)k * n + l];
-    for (int jj = tid; jj < n; jj += nthr) c1 += R1[(int64_t)jj * m + k];
-    s3 = slab_sum(s3);
-    c1 = slab_sum(c1);
-    if (tid == 0) {
-      vec[vec_PR3(G) + k] = s3;
-      vec[vec_Sp(G) + k] = c1 + s3;
+    if (wide && wave != 0) p0 = p1 = p2 = 0.0;  // (every wave holds the slab totals)
+    if (lane == 0) {
+      wred[wave][0] = p0;
+      wred[wave][1] = p1;
+      wred[wave][2] = p2;
     }
-    p1 = s3;
-    p2 = (c1 + s3) * dinv(m, k);
+    __syncthreads();
+    if (threadIdx.x < 3)
+      vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
   }
-  if (wide && wave != 0) p0 = p1 = p2 = 0.0;  // (every wave holds the slab totals)
-  if (lane == 0) {
-    wred[wave][0] = p0;
-    wred[wave][1] = p1;
-    wred[wave][2] = p2;
-  }
-  __syncthreads();
-  if (threadIdx.x < 3)
-    vec[vec_spart(G) + 4 * (int64_t)slot + threadIdx.x] = wave4(wred, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -31,7 +31,7 @@ struct Tuning {
                         // wave-per-slab (whole slab per wave, no block barriers)
   int batch_groups;     // concurrent groups (streams) a batch is split into
   int fuse;             // default for one slab kernel for every pass
-  int solve_spw;        // > 0: slabs per wave of the solve row blocks (else by pair size)
+  int row_group;        // > 0: slabs per solve wave and slots per reduce block (else by launch size)
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries

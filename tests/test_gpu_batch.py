@@ -54,17 +54,18 @@ def test_fused_and_split_slab_kernels_bitwise(monkeypatch):
             assert torch.equal(t0, t1)
 
 
-def test_solve_slabs_per_wave_bitwise(monkeypatch):
-    """Solve row blocks of one or four slabs per wave compute every slab's
-    beta the same way: identical results (the default picks four for
-    launches with many row blocks)."""
+def test_row_grouping_bitwise(monkeypatch):
+    """Solve waves of one, three or four slabs and reduce blocks of as many
+    slots compute every slab's values and every slot's partials the same
+    way: identical results (the default groups four for launches with many
+    row blocks)."""
     need_gpu()
     from paper_2408_00598_amd import hot, workloads
     pairs = workloads.batch_pairs(8, sides=(16, 40, 72, 130))
     dp = [(dev(a), dev(b)) for a, b in pairs]
     ctxs = []
     for spw in ("1", "4", "3"):
-        monkeypatch.setenv("HOT_SOLVE_SPW", spw)
+        monkeypatch.setenv("HOT_ROW_GROUP", spw)
         ctxs.append(hot.Context(0))
     for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
         rs = [c.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec) for c in ctxs]
