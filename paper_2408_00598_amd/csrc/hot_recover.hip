@@ -7,11 +7,15 @@
 // amount.  That greedy rule is the north-west-corner coupling of the two
 // sequences: with P_i, Q_l their running totals, source i and target l
 // exchange the overlap of (P_{i-1}, P_i] and (Q_{l-1}, Q_l].  One wave owns
-// one bin: it stages both running totals in LDS (FP64) and each lane walks
-// its sources (or targets) from a binary-searched start.  Entries are
-// counted, offsets come from a scan, and a second walk writes them, so the
-// output order is fixed: bins in (k*n + j) order, then source i, then
-// target l.  The flows are the clipped max(x_bar, 0) of the solution.
+// one bin: it stages both running totals in LDS (FP64).  The entries are the
+// segments between consecutive values of the merged totals; the wave takes
+// them 64 at a time (merge-path search per lane, a ballot to skip empty
+// ones), so both the count and the write pass are balanced across lanes and
+// the write is contiguous.  The scaled marginal passes walk each source's
+// (or target's) overlaps from a binary-searched start.  Entries are counted,
+// offsets come from a scan, and the write pass emits them in a fixed order:
+// bins in (k*n + j) order, then source i, then target l.  The flows are the
+// clipped max(x_bar, 0) of the solution.
 //
 // Repair (the algorithm assumes an exactly optimal, feasible flow): rows
 // whose total exceeds mu1 are scaled down, then columns above mu2, and the
@@ -92,6 +96,23 @@ __device__ inline void stage_prefix(const double* __restrict__ src, int len, dou
     out[1 + t] = run;
   }
   __syncthreads();
+  // The lanes' totals are rounded in different orders, so where flows are
+  // zero a total can sit a rounding step below its predecessor.  A running
+  // maximum (exact in any order) makes the totals nondecreasing, as the
+  // searches over them assume.
+  double mx = 0.0;
+  for (int t = b0; t < b1; ++t) mx = fmax(mx, out[1 + t]);
+  for (int off = 1; off < 64; off <<= 1) {
+    const double v = __shfl_up(mx, off, 64);
+    if (lane >= off) mx = fmax(mx, v);
+  }
+  double rm = __shfl_up(mx, 1, 64);
+  if (lane == 0) rm = 0.0;
+  for (int t = b0; t < b1; ++t) {
+    rm = fmax(rm, out[1 + t]);
+    out[1 + t] = rm;
+  }
+  __syncthreads();
 }
 
 // smallest index l in [0, n) with Q[l+1] > v, or n
@@ -105,6 +126,49 @@ __device__ inline int first_above(const double* Q, int n, double v) {
 }
 
 enum RecPass { PASS_COUNT = 0, PASS_COLSCALED = 1, PASS_BOTHSCALED = 2, PASS_WRITE = 3 };
+
+// The bin's coupling entries in order, 64 candidates per call.  Candidate t
+// (t < m + n) is the segment (e_{t-1}, e_t] between consecutive values of the
+// merged running totals {P[1..m]} and {Q[1..n]} (e_{-1} = 0); it is an entry
+// when it has positive length and lies inside both totals: then it is the
+// overlap of source i = #{P[1..m] <= e_{t-1}} and target l likewise, exactly
+// min(P[i+1], Q[l+1]) - max(P[i], Q[l]).  Entries come out in the order of
+// Algorithm 1's walk (source, then target), and a wave writes them to
+// consecutive positions.  `prev` carries e of the previous chunk's last lane.
+struct Seg {
+  bool ok;
+  int i, l;
+  double lo, hi;  // the segment (lo, hi]
+};
+__device__ inline Seg bin_segment(const double* P, const double* Q, int m, int n, int t,
+                                  int lane, double& prev) {
+  double e = 0.0;
+  if (t < m + n) {
+    // merge path: a of the k = t + 1 smallest come from P (ties: P first)
+    const int k = t + 1;
+    int lo = max(0, k - n), hi = min(k, m);
+    while (lo < hi) {
+      const int a = (lo + hi) >> 1;
+      if (P[a + 1] <= Q[k - a]) lo = a + 1; else hi = a;
+    }
+    e = fmax(P[lo], Q[k - lo]);
+  }
+  double u = __shfl_up(e, 1, 64);
+  if (lane == 0) u = prev;
+  prev = __shfl(e, 63, 64);
+  Seg sg;
+  sg.ok = false;
+  sg.i = m;
+  sg.l = n;
+  sg.lo = u;
+  sg.hi = e;
+  if (t < m + n && e > u) {
+    sg.i = first_above(P, m, u);
+    sg.l = first_above(Q, n, u);
+    sg.ok = sg.i < m && sg.l < n;
+  }
+  return sg;
+}
 
 // One wave per bin (k, j), item = k*n + j.
 template <int PASS>
@@ -128,21 +192,23 @@ __global__ __launch_bounds__(64) void k_rec_bin(int m, int n, const double* __re
   double* Q = lds + (m + 1);
   stage_prefix(a, m, P, lane);
   stage_prefix(b, n, Q, lane);
+  // scale factors of this bin's sources and targets (small, L2-resident)
+  const double* R = PASS != PASS_COUNT ? rho_r + (int64_t)j * m : nullptr;
+  const double* C = PASS >= PASS_BOTHSCALED ? rho_c + (int64_t)k * n : nullptr;
   const double PT = P[m], QT = Q[n];
   double* m1 = mt + (int64_t)j * m * m + (int64_t)k * m;
   double* m2 = mt + N1 + (int64_t)k * n * n + (int64_t)j * n;
   if (PASS == PASS_COUNT) {
-    long long cnt = 0;
-    for (int i = lane; i < m; i += 64) {
-      const double lo = P[i], hi = P[i + 1];
-      // matched amount of source i: its interval clipped to (0, QT]
-      m1[i] = fmax(0.0, fmin(hi, QT) - fmin(lo, QT));
-      if (!(hi > lo)) continue;
-      for (int l = first_above(Q, n, lo); l < n && Q[l] < hi; ++l)
-        if (fmin(hi, Q[l + 1]) - fmax(lo, Q[l]) > 0.0) ++cnt;
-    }
+    // matched amount of source i: its interval clipped to (0, QT]; of target
+    // l likewise clipped to (0, PT]
+    for (int i = lane; i < m; i += 64) m1[i] = fmax(0.0, fmin(P[i + 1], QT) - fmin(P[i], QT));
     for (int l = lane; l < n; l += 64) m2[l] = fmax(0.0, fmin(Q[l + 1], PT) - fmin(Q[l], PT));
-    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    long long cnt = 0;
+    double prev = 0.0;
+    for (int t0 = 0; t0 < m + n; t0 += 64) {
+      const Seg sg = bin_segment(P, Q, m, n, t0 + lane, lane, prev);
+      cnt += __popcll(__ballot(sg.ok));
+    }
     if (lane == 0) counts[item] = cnt;
   } else if (PASS == PASS_COLSCALED) {
     // target-centric: sum_i pi_{i,l} rho_r(i,j)
@@ -152,7 +218,7 @@ __global__ __launch_bounds__(64) void k_rec_bin(int m, int n, const double* __re
       if (hi > lo)
         for (int i = first_above(P, m, lo); i < m && P[i] < hi; ++i) {
           const double ov = fmin(P[i + 1], hi) - fmax(P[i], lo);
-          if (ov > 0.0) acc += ov * rho_r[(int64_t)j * m + i];
+          if (ov > 0.0) acc += ov * R[i];
         }
       m2[l] = acc;
     }
@@ -163,7 +229,7 @@ __global__ __launch_bounds__(64) void k_rec_bin(int m, int n, const double* __re
       if (hi > lo)
         for (int l = first_above(Q, n, lo); l < n && Q[l] < hi; ++l) {
           const double ov = fmin(hi, Q[l + 1]) - fmax(lo, Q[l]);
-          if (ov > 0.0) acc += ov * rho_r[(int64_t)j * m + i] * rho_c[(int64_t)k * n + l];
+          if (ov > 0.0) acc += ov * R[i] * C[l];
         }
       m1[i] = acc;
     }
@@ -173,45 +239,23 @@ __global__ __launch_bounds__(64) void k_rec_bin(int m, int n, const double* __re
       if (hi > lo)
         for (int i = first_above(P, m, lo); i < m && P[i] < hi; ++i) {
           const double ov = fmin(P[i + 1], hi) - fmax(P[i], lo);
-          if (ov > 0.0) acc += ov * rho_r[(int64_t)j * m + i] * rho_c[(int64_t)k * n + l];
+          if (ov > 0.0) acc += ov * R[i] * C[l];
         }
       m2[l] = acc;
     }
-  } else {  // PASS_WRITE: rounds of 64 sources, ordered by i then l
+  } else {  // PASS_WRITE: the entries in order, 64 candidates per step
     long long base = offsets[item];
-    for (int i0 = 0; i0 < m; i0 += 64) {
-      const int i = i0 + lane;
-      long long cnt = 0;
-      double lo = 0.0, hi = 0.0;
-      int lstart = n;
-      if (i < m) {
-        lo = P[i];
-        hi = P[i + 1];
-        if (hi > lo) {
-          lstart = first_above(Q, n, lo);
-          for (int l = lstart; l < n && Q[l] < hi; ++l)
-            if (fmin(hi, Q[l + 1]) - fmax(lo, Q[l]) > 0.0) ++cnt;
-        }
+    double prev = 0.0;
+    for (int t0 = 0; t0 < m + n; t0 += 64) {
+      const Seg sg = bin_segment(P, Q, m, n, t0 + lane, lane, prev);
+      const unsigned long long mask = __ballot(sg.ok);
+      if (sg.ok) {
+        const long long pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+        osrc[pos] = sg.i * n + j;
+        odst[pos] = k * n + sg.l;
+        omass[pos] = (sg.hi - sg.lo) * R[sg.i] * C[sg.l];
       }
-      long long incl = cnt;
-      for (int off = 1; off < 64; off <<= 1) {
-        const long long v = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += v;
-      }
-      long long pos = base + incl - cnt;
-      if (i < m && hi > lo) {
-        const double rr = rho_r[(int64_t)j * m + i];
-        for (int l = lstart; l < n && Q[l] < hi; ++l) {
-          const double ov = fmin(hi, Q[l + 1]) - fmax(lo, Q[l]);
-          if (ov > 0.0) {
-            osrc[pos] = i * n + j;
-            odst[pos] = k * n + l;
-            omass[pos] = ov * rr * rho_c[(int64_t)k * n + l];
-            ++pos;
-          }
-        }
-      }
-      base += __shfl(incl, 63, 64);
+      base += __popcll(mask);
     }
   }
 }
@@ -469,7 +513,7 @@ extern "C" hot_status hot_recover_plan(hot_ctx* ctx, const hot_solution* sol, ho
     hipLaunchKernelGGL(k_clip_flows<double>, dim3(grid_for(N)), dim3(256), 0, st, a.geo,
                        a.ctl[0], pair, (const double*)a.sb[0], (const double*)a.sb[1],
                        (const double*)a.sb[2], a.ab, w);
-  const size_t lds = (size_t)(m + n + 2) * sizeof(double);
+  const size_t lds = (size_t)(m + n + 2) * sizeof(double);  // P, Q
   // pass A: counts and matched amounts -> raw marginals r (layout [j][i]), c ([k][l])
   hipLaunchKernelGGL(k_rec_bin<PASS_COUNT>, dim3((unsigned)M), dim3(64), lds, st, m, n, w, mt,
                      counts, (const long long*)nullptr, (const double*)nullptr,
