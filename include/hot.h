@@ -121,7 +121,18 @@ typedef struct hot_batch hot_batch;
 typedef struct hot_server hot_server;
 
 /* Create a context on HIP device `device`.  Owns the workspace pool.
- * Returns HOT_E_DEVICE if the device cannot be used (e.g. no GPU). */
+ * Returns HOT_E_DEVICE if the device cannot be used (e.g. no GPU).
+ * Launch-shape defaults can be overridden through environment variables read
+ * here (integers; for measurement and tuning, none changes a result beyond
+ * summation order): HOT_ITEM_ELEMS (flow elements per slab-pass workgroup),
+ * HOT_MIN_ITEMS, HOT_UNROLL (1 or 2 rows per wave step), HOT_VPL_TARGET
+ * (16-byte vectors per lane per row), HOT_NT_STORE (0/1), HOT_PINGPONG (0/1),
+ * HOT_SMALL_SIDE (largest slab side of the wave-per-slab pass, 0 = none),
+ * HOT_FUSE (0: separate plain and check/restart slab kernels),
+ * HOT_ROW_GROUP (slabs per solve wave and slots per reduce block; results
+ * unchanged), HOT_BATCH_GROUPS (1..4 concurrent groups of a batch).
+ * HOT_NO_GRAPH=1 launches every iteration directly instead of through
+ * captured graphs. */
 hot_status hot_ctx_create(int device, hot_ctx **out);
 void hot_ctx_destroy(hot_ctx *ctx);
 
