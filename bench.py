@@ -87,8 +87,9 @@ def make_workload(name, pairs):
 def describe(base, prec, tol, sigma_update):
     from paper_2408_00598_amd import hot
     p = "FP32 streams + FP64 reductions" if prec == hot.HOT_FP32_STREAM else "FP64"
-    return f"{base}, {p}, rel KKT {tol:g}" + (", sigma re-balanced at restarts"
-                                              if sigma_update else "")
+    t = ("%.0e" % tol).replace("e-0", "e-").replace("e+0", "e") if tol > 0 else str(tol)
+    return f"{base}, {p}, rel KKT {t}" + (", sigma re-balanced at restarts"
+                                          if sigma_update else "")
 
 
 def run_serving(args):

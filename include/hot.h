@@ -129,8 +129,9 @@ typedef struct hot_server hot_server;
  * (16-byte vectors per lane per row), HOT_NT_STORE (0/1), HOT_PINGPONG (0/1),
  * HOT_SMALL_SIDE (largest slab side of the wave-per-slab pass, 0 = none),
  * HOT_FUSE (0: separate plain and check/restart slab kernels),
- * HOT_ROW_GROUP (slabs per solve wave and slots per reduce block; results
- * unchanged), HOT_BATCH_GROUPS (1..4 concurrent groups of a batch).
+ * HOT_ROW_GROUP (slabs per solve wave; results unchanged), HOT_REDUCE_GROUP
+ * (row slots per reduce workgroup; results unchanged), HOT_BATCH_GROUPS (1..4
+ * concurrent groups of a batch).
  * HOT_NO_GRAPH=1 launches every iteration directly instead of through
  * captured graphs. */
 hot_status hot_ctx_create(int device, hot_ctx **out);

@@ -32,6 +32,7 @@ struct Tuning {
   int batch_groups;     // concurrent groups (streams) a batch is split into
   int fuse;             // default for one slab kernel for every pass
   int row_group;        // > 0: slabs per solve wave and slots per reduce block (else by launch size)
+  int reduce_group;     // > 0: slots per reduce block (overrides row_group for the reduce)
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
