@@ -64,8 +64,9 @@ def test_row_grouping_bitwise(monkeypatch):
     pairs = workloads.batch_pairs(8, sides=(16, 40, 72, 130))
     dp = [(dev(a), dev(b)) for a, b in pairs]
     ctxs = []
-    for spw in ("1", "4", "3"):
+    for spw, rq in (("1", "1"), ("4", "4"), ("3", "2")):
         monkeypatch.setenv("HOT_ROW_GROUP", spw)
+        monkeypatch.setenv("HOT_REDUCE_GROUP", rq)
         ctxs.append(hot.Context(0))
     for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
         rs = [c.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec) for c in ctxs]
