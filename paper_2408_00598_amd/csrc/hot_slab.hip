@@ -163,8 +163,8 @@ __device__ __forceinline__ void slab_rows(const SlabCtx& x, const T* __restrict_
 // both are launched every iteration, a workgroup whose pair is in the other
 // kind of pass exits at once).  HEAVY = 2: every pass kind in one kernel,
 // check and restart rows streamed one row step at a time as in HEAVY = 1;
-// its register count stays that of the plain kernel, and the launch it saves
-// is worth 2-4% of a solve.  The three are forced inline into their kernels:
+// on uniform bins its register count stays that of the plain kernel, and the
+// launch it saves is worth 2-6% of a solve.  The three are forced inline into their kernels:
 // a second caller would otherwise turn slab_item into a real call, which
 // more than doubles the register count.
 template <typename T, int MAXVPL, int HEAVY, int U, int C, int SU>
@@ -522,13 +522,32 @@ static void launch_fused(const LaunchArgs& a, int par, hipStream_t st) {
 
 template <typename T, int V>
 static void launch_slab(const LaunchArgs& a, int par, hipStream_t st) {
-  if (a.fuse && !a.coord && !a.su) {
+  if (a.fuse && a.coord) {  // non-uniform bins: one row per wave step
+    if (a.nt_store) {
+      if (a.su) launch_fused<T, V, 5, 1, 1>(a, par, st);
+      else launch_fused<T, V, 5, 1, 0>(a, par, st);
+    } else {
+      if (a.su) launch_fused<T, V, 1, 1, 1>(a, par, st);
+      else launch_fused<T, V, 1, 1, 0>(a, par, st);
+    }
+    return;
+  }
+  if (a.fuse) {
     const int u = (a.unroll >= 2 ? 2 : 1) | (a.nt_store ? 4 : 0);
-    switch (u) {
-      case 1: launch_fused<T, V, 1, 0, 0>(a, par, st); break;
-      case 2: launch_fused<T, V, 2, 0, 0>(a, par, st); break;
-      case 5: launch_fused<T, V, 5, 0, 0>(a, par, st); break;
-      default: launch_fused<T, V, 6, 0, 0>(a, par, st); break;
+    if (a.su) {
+      switch (u) {
+        case 1: launch_fused<T, V, 1, 0, 1>(a, par, st); break;
+        case 2: launch_fused<T, V, 2, 0, 1>(a, par, st); break;
+        case 5: launch_fused<T, V, 5, 0, 1>(a, par, st); break;
+        default: launch_fused<T, V, 6, 0, 1>(a, par, st); break;
+      }
+    } else {
+      switch (u) {
+        case 1: launch_fused<T, V, 1, 0, 0>(a, par, st); break;
+        case 2: launch_fused<T, V, 2, 0, 0>(a, par, st); break;
+        case 5: launch_fused<T, V, 5, 0, 0>(a, par, st); break;
+        default: launch_fused<T, V, 6, 0, 0>(a, par, st); break;
+      }
     }
     return;
   }
