@@ -54,6 +54,34 @@ def test_fused_and_split_slab_kernels_bitwise(monkeypatch):
             assert torch.equal(t0, t1)
 
 
+@pytest.mark.parametrize("variant", ["sigma_update", "nonuniform", "both"])
+def test_fused_and_split_variants_bitwise(monkeypatch, variant):
+    """The same for sigma re-balancing at restarts and non-uniform bins (the
+    variants whose check and restart rows carry extra work)."""
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    rng = np.random.default_rng(workloads.seed_for(0, 77))
+    m, n = 40, 72
+    a = dev(workloads.gaussian_blobs(m, n, 3, rng))
+    b = dev(workloads.gaussian_blobs(m, n, 3, rng))
+    kw = dict(tol=1e-6, max_iter=20000)
+    if variant != "nonuniform":
+        kw["flags"] = hot.HOT_FLAG_RESTART | hot.HOT_FLAG_SIGMA_UPDATE
+    if variant != "sigma_update":
+        kw["coord_row"] = dev(workloads.grid_lines(m, rng))
+        kw["coord_col"] = dev(workloads.grid_lines(n, rng))
+    res = []
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("HOT_FUSE", fuse)
+        c = hot.Context(0)
+        res.append([c.solve(a, b, prec=p, **kw)[0] for p in (hot.HOT_FP64, hot.HOT_FP32_STREAM)])
+    # (converged or stopped at max_iter alike: restarts and check passes ran)
+    assert res[0][0]["restarts"] > 0
+    for ra, rb in zip(*res):
+        for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
+            assert ra[key] == rb[key], (variant, key, ra[key], rb[key])
+
+
 def test_row_grouping_bitwise(monkeypatch):
     """Solve waves of one, three or four slabs and reduce blocks of as many
     slots compute every slab's values and every slot's partials the same
