@@ -94,7 +94,7 @@ Tuning default_tuning() {
   t.nt_store = 1;
   t.pingpong = 1;
   t.sep_anchor = 0;
-  t.small_side = 64;
+  t.small_side = 48;
   t.batch_groups = 2;
   t.fuse = 1;
   t.row_group = 0;

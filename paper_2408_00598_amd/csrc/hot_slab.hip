@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kWG) void k_slab_pass(
 }
 
 // ---------------------------------------------------------------------------
-// Wave-per-slab plain-update pass for small slabs (side <= a tunable, 64 by
+// Wave-per-slab plain-update pass for small slabs (side <= a tunable, 48 by
 // default).  A block pass over a 32 x 32 slab keeps most of a workgroup idle
 // and pays two barriers and an LDS round trip for 4 KB of state; here each
 // wave owns a whole slab: beta (and the column positions) sit in registers
