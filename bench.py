@@ -204,10 +204,11 @@ def measured_traffic(workload, launch):
         return None
 
 
-def cpu_baseline(pairs, results, tol, budget_s=20.0):
-    """Oracle (FP64, single thread) seconds per iteration measured per grid
-    side on the first pair of that side, times the iterations each pair took,
-    summed over the batch."""
+def cpu_baseline(pairs, results, tol, budget_s=20.0, threads=False):
+    """Oracle (FP64, single thread; threads: its OpenMP build, the same source
+    on the host's cores) seconds per iteration measured per grid side on the
+    first pair of that side, times the iterations each pair took, summed over
+    the batch."""
     from oracle import oracle as O
     sides = sorted({a.shape for a, _ in pairs})
     per_side = {}
@@ -217,7 +218,7 @@ def cpu_baseline(pairs, results, tol, budget_s=20.0):
         k, t = 1, 0.0
         while True:
             t0 = time.perf_counter()
-            O.hot(a, b, fixed_iters=k, restart=False)
+            O.hot(a, b, fixed_iters=k, restart=False, threads=threads)
             t = time.perf_counter() - t0
             if t >= share / 4 or k >= 4096:
                 break
@@ -227,7 +228,9 @@ def cpu_baseline(pairs, results, tol, budget_s=20.0):
     sample = ("oracle s/iteration timed on one pair per grid side ("
               + ", ".join(f"{s[0]}x{s[1]}: {per_side[s]*1e3:.2f} ms/it" for s in sides)
               + ") x the iterations each pair took on the GPU, summed over the batch")
-    return {"value": len(pairs) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count()) if threads else 1
+    return {"value": len(pairs) / total, "unit": "solves/s", "cores": cores,
+            "kind": "oracle, OpenMP build of the same source" if threads else "oracle",
             "sample": sample, "estimated_seconds": total}
 
 
@@ -399,6 +402,7 @@ def main():
                                    "GB/s": 2 * 4 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs, results, tol)
+        out["cpu_baseline_multicore"] = cpu_baseline(pairs, results, tol, threads=True)
     print(json.dumps(out), flush=True)
 
 

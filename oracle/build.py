@@ -10,25 +10,31 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libhot_oracle.so")
+LIB_OMP = os.path.join(OUT_DIR, "libhot_oracle_omp.so")  # same source, -fopenmp
 SRC = os.path.join(HERE, "hot_oracle.c")
 
 
 def build(openmp: bool = False, quiet: bool = True) -> str:
+    """The serial oracle, or (openmp) the same source with its independent
+    loops on several threads, for multi-core timing only."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    out = LIB
+    out = LIB_OMP if openmp else LIB
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-fno-fast-math", SRC, "-o", out + ".tmp", "-lm"]
+           "-fno-fast-math", *(["-fopenmp"] if openmp else []), SRC, "-o", out + ".tmp",
+           "-lm"]
     subprocess.run(cmd, check=True, capture_output=quiet)
     os.replace(out + ".tmp", out)
     return out
 
 
-def ensure_built() -> str:
-    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        build()
-    return LIB
+def ensure_built(openmp: bool = False) -> str:
+    lib = LIB_OMP if openmp else LIB
+    if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        build(openmp=openmp)
+    return lib
 
 
 if __name__ == "__main__":
     print(build(quiet=False))
+    print(build(openmp=True, quiet=False))
     sys.exit(0)

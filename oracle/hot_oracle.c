@@ -23,6 +23,17 @@
 /* ------------------------------------------------------------------ */
 
 /* f1_{i,k,j}: flow from bin (i,j) to bin (k,j) */
+/* Built with -fopenmp (the multi-core timing build), the loops marked here
+ * run their independent iterations on several threads: each marked loop
+ * writes disjoint outputs and computes every output with the same sequential
+ * code as the serial build, so both builds give bit-identical results.  The
+ * reductions (norms, inner products) stay sequential. */
+#ifdef _OPENMP
+#define OR_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define OR_PARALLEL_FOR
+#endif
+
 static int64_t ix1(int32_t m, int32_t n, int32_t i, int32_t k, int32_t j) {
   (void)n;
   return ((int64_t)j * m + k) * m + i;
@@ -81,6 +92,7 @@ void or_bvec(int32_t m, int32_t n, const double *mu1, const double *mu2,
 void or_A(int32_t m, int32_t n, const double *x, double *out) {
   const int64_t M = (int64_t)m * n;
   /* rows A1/A2: sum_i f1_{i,k,j} - sum_l f2_{k,j,l} for bin (k,j) */
+  OR_PARALLEL_FOR
   for (int32_t j = 0; j < n; ++j)
     for (int32_t k = 0; k < m; ++k) {
       double acc = 0.0;
@@ -89,6 +101,7 @@ void or_A(int32_t m, int32_t n, const double *x, double *out) {
       out[(int64_t)j * m + k] = acc;
     }
   /* rows A3: sum_k f1_{i,k,j} for bin (i,j) */
+  OR_PARALLEL_FOR
   for (int32_t j = 0; j < n; ++j)
     for (int32_t i = 0; i < m; ++i) {
       double acc = 0.0;
@@ -96,6 +109,7 @@ void or_A(int32_t m, int32_t n, const double *x, double *out) {
       out[M + (int64_t)j * m + i] = acc;
     }
   /* rows A4: sum_j f2_{k,j,l} for bin (k,l), last row dropped */
+  OR_PARALLEL_FOR
   for (int32_t l = 0; l < n; ++l)
     for (int32_t k = 0; k < m; ++k) {
       if (l == n - 1 && k == m - 1) continue;
@@ -108,10 +122,12 @@ void or_A(int32_t m, int32_t n, const double *x, double *out) {
 /* A^T y: every flow variable appears in exactly two rows of A. */
 void or_AT(int32_t m, int32_t n, const double *y, double *out) {
   const int64_t M = (int64_t)m * n;
+  OR_PARALLEL_FOR
   for (int32_t j = 0; j < n; ++j)
     for (int32_t k = 0; k < m; ++k)
       for (int32_t i = 0; i < m; ++i)
         out[ix1(m, n, i, k, j)] = y[(int64_t)j * m + k] + y[M + (int64_t)j * m + i];
+  OR_PARALLEL_FOR
   for (int32_t k = 0; k < m; ++k)
     for (int32_t j = 0; j < n; ++j)
       for (int32_t l = 0; l < n; ++l) {
@@ -304,14 +320,17 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   memset(res, 0, sizeof(*res));
   for (;;) {
     /* Step 1: A A^T y_bar = b/sigma - A(x/sigma + z - c) */
+    OR_PARALLEL_FOR
     for (int64_t e = 0; e < N; ++e) tmp[e] = x[e] / sigma + z[e] - c[e];
     or_A(m, n, tmp, R);
     for (int64_t q = 0; q < M3; ++q) R[q] = b[q] / sigma - R[q];
     or_solve_aat(m, n, R, ybar);
     /* Step 2 */
     or_AT(m, n, ybar, aty);
+    OR_PARALLEL_FOR
     for (int64_t e = 0; e < N; ++e) xbar[e] = x[e] + sigma * (aty[e] + z[e] - c[e]);
     /* Step 3 */
+    OR_PARALLEL_FOR
     for (int64_t e = 0; e < N; ++e) {
       double v = c[e] - aty[e] - xbar[e] / sigma;
       zbar[e] = v > 0.0 ? v : 0.0;
@@ -376,6 +395,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
       /* generalized ADMM baseline of the experiments (Sec. 4.1): Step 4
        * replaced by w^{k+1} = (1 - rho) w^k + rho w_bar^k */
       const double rho = p->admm_rho;
+      OR_PARALLEL_FOR
       for (int64_t e = 0; e < N; ++e) {
         x[e] = (1.0 - rho) * x[e] + rho * xbar[e];
         z[e] = (1.0 - rho) * z[e] + rho * zbar[e];
@@ -384,6 +404,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
     } else {
       /* Step 4: w^{k+1} = w^0/(k+2) + (k+1)/(k+2) (2 w_bar - w) */
       const double a = 1.0 / (double)(k + 2), bb = (double)(k + 1) / (double)(k + 2);
+      OR_PARALLEL_FOR
       for (int64_t e = 0; e < N; ++e) {
         x[e] = a * x0[e] + bb * (2.0 * xbar[e] - x[e]);
         z[e] = a * z0[e] + bb * (2.0 * zbar[e] - z[e]);

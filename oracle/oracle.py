@@ -10,7 +10,7 @@ import numpy as np
 
 from .build import ensure_built
 
-_lib = None
+_libs = {}
 
 D = C.POINTER(C.c_double)
 I32 = C.POINTER(C.c_int32)
@@ -36,11 +36,11 @@ class Result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        _lib = C.CDLL(ensure_built())
-        L = _lib
+def lib(openmp=False):
+    """The serial oracle, or its OpenMP build (same source, identical results;
+    for multi-core timing)."""
+    if openmp not in _libs:
+        L = C.CDLL(ensure_built(openmp))
         L.or_dims.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.or_cost.argtypes = [C.c_int32, C.c_int32, D]
         L.or_cost_xy.argtypes = [C.c_int32, C.c_int32, D, D, D]
@@ -62,7 +62,8 @@ def lib():
         L.or_simplex.restype = C.c_int32
         L.or_w2_1d.argtypes = [C.c_int32, D, D]
         L.or_w2_1d.restype = C.c_double
-    return _lib
+        _libs[openmp] = L
+    return _libs[openmp]
 
 
 def _d(a):
@@ -153,8 +154,9 @@ def kkt(mu1, mu2, x, y, z, coord_row=None, coord_col=None):
 
 def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
         restart=True, fixed_iters=0, admm_rho=0.0, abs_kkt=False, coord_row=None,
-        coord_col=None, sigma_update=False):
-    """Run Algorithm 2; returns (xbar, ybar, zbar, s_state, result dict)."""
+        coord_col=None, sigma_update=False, threads=False):
+    """Run Algorithm 2; returns (xbar, ybar, zbar, s_state, result dict).
+    threads: the OpenMP build (multi-core timing; identical results)."""
     mu1, mu2 = _f64(mu1), _f64(mu2)
     m, n = mu1.shape
     N, M3 = dims(m, n)
@@ -164,8 +166,8 @@ def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
     p = Params(tol, max_iter, check_every, sigma, 1 if restart else 0, fixed_iters, admm_rho,
                1 if abs_kkt else 0, _dn(u), _dn(v), 1 if sigma_update else 0)
     r = Result()
-    lib().or_hot(m, n, _d(mu1), _d(mu2), C.byref(p), _d(xb), _d(yb), _d(zb), _d(s),
-                 C.byref(r))
+    lib(threads).or_hot(m, n, _d(mu1), _d(mu2), C.byref(p), _d(xb), _d(yb), _d(zb), _d(s),
+                        C.byref(r))
     return xb, yb, zb, s, r.as_dict()
 
 
