@@ -144,6 +144,15 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   // four)
   int64_t rows4 = 0;
   for (const auto& sh : shapes) rows4 += (sh.first + sh.second + 3) / 4;
+  // the wave-per-slab pass costs a launch of its own each iteration: worth it
+  // only for launches with many small slabs (256-pair batch: ~8,000; a lone
+  // 32 x 32 pair, 64 slabs, is 13% faster without it)
+  int64_t small_slabs = 0;
+  for (const auto& sh : shapes) {
+    if (sh.first <= tune.small_side) small_slabs += sh.second;   // F1: n slabs of side m
+    if (sh.second <= tune.small_side) small_slabs += sh.first;   // F2: m slabs of side n
+  }
+  const int small_side = small_slabs >= kMinSmallSlabs ? tune.small_side : 0;
   const int row_group = tune.row_group > 0 ? tune.row_group : (rows4 > 2048 ? 4 : 1);
   for (size_t p = 0; p < shapes.size(); ++p) {
     const int m = shapes[p].first, n = shapes[p].second;
@@ -167,7 +176,7 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
       F.vpl = vpl;
       maxvpl = std::max(maxvpl, vpl);
       const int step = 8 * (64 / LR);  // rows one workgroup covers per (two-row) step
-      const bool small = F.L <= tune.small_side;  // whole slab per wave
+      const bool small = F.L <= small_side;  // whole slab per wave
       int rows = (int)std::max<int64_t>(1, item_elems / F.P);
       rows = (int)round_up(rows, step);
       if (rows >= F.L || small) rows = F.L;

@@ -28,6 +28,7 @@ constexpr int kKP = 12;         // per-block partials written by the pair reduce
 constexpr int kMaxSide = 1024;  // largest supported m or n
 constexpr int kWideSide = 256;  // slab side from which the pair reduce gives a
                                 // slab a whole workgroup instead of one wave
+constexpr int kMinSmallSlabs = 1024;  // fewest small slabs for the wave-per-slab pass
 
 enum Mode : int32_t {
   MODE_IDLE = 0,

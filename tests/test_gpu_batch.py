@@ -30,7 +30,9 @@ def test_fused_and_split_slab_kernels_bitwise(monkeypatch):
     need_gpu()
     import torch
     from paper_2408_00598_amd import hot, workloads
-    pairs = workloads.batch_pairs(6, sides=(24, 48, 96, 130))
+    pairs = workloads.batch_pairs(40, sides=(16, 24, 32, 48, 96, 130))
+    # enough small slabs (side <= 48) for the launch to take the wave-per-slab pass
+    assert sum(2 * a.shape[0] for a, _ in pairs if a.shape[0] <= 48) >= 1024
     dp = [(dev(a), dev(b)) for a, b in pairs]
     ctxs = []
     for fuse in ("0", "1"):
