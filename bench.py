@@ -11,6 +11,8 @@ Workloads (named by what they are):
             blob mixtures and half U(0,1) noise, FP32 streams, rel KKT 1e-4
             (the default; the headline "FP32 batched" figure)
   pair128   one 128 x 128 pair (5 blobs), FP32 streams, rel KKT 1e-4
+  pair128nu the same pair on non-uniform bins (Gamma-spaced grid lines)
+  pair128noise  one 128 x 128 pair of U(0,1) noise
   pair512   one 512 x 512 pair (1-8 blobs + Cauchy blob), FP32, rel KKT 1e-4
   small     one 32 x 32 pair (3 blobs), FP64, rel KKT 1e-6
   serving   Poisson arrivals (200/s for --duration s), side in {64,96,128,192,256},
@@ -72,6 +74,10 @@ def make_workload(name, pairs):
     if name == "pair128":
         return ([workloads.pair_medium("blobs")], 1e-4, hot.HOT_FP32_STREAM,
                 "one 128x128 pair, 5 Gaussian blobs + floor 1e-3")
+    if name == "pair128nu":
+        return ([workloads.pair_medium("blobs")], 1e-4, hot.HOT_FP32_STREAM,
+                "one 128x128 pair, 5 Gaussian blobs + floor 1e-3, non-uniform bins "
+                "(Gamma(0.7) line gaps)")
     if name == "pair128noise":
         return ([workloads.pair_medium("noise")], 1e-4, hot.HOT_FP32_STREAM,
                 "one 128x128 pair, U(0,1) noise")
@@ -292,6 +298,12 @@ def main():
     ctx = hot.Context(0)
     flags = hot.HOT_FLAG_RESTART | (hot.HOT_FLAG_SIGMA_UPDATE if args.sigma_update else 0)
     kw = dict(tol=tol, max_iter=1000000, prec=prec, flags=flags)
+    if args.workload == "pair128nu":  # grid-line positions of the non-uniform bins
+        from paper_2408_00598_amd import workloads
+        rng = np.random.default_rng(workloads.seed_for(1, 900))
+        m, n = pairs[0][0].shape
+        kw["coord_row"] = torch.tensor(workloads.grid_lines(m, rng), device=dev)
+        kw["coord_col"] = torch.tensor(workloads.grid_lines(n, rng), device=dev)
 
     plan_stats = []
 
