@@ -12,6 +12,7 @@ Workloads (named by what they are):
             (the default; the headline "FP32 batched" figure)
   pair128   one 128 x 128 pair (5 blobs), FP32 streams, rel KKT 1e-4
   pair128nu the same pair on non-uniform bins (Gamma-spaced grid lines)
+  pair64    one 64 x 64 pair (5 blobs)
   pair128noise  one 128 x 128 pair of U(0,1) noise
   pair512   one 512 x 512 pair (1-8 blobs + Cauchy blob), FP32, rel KKT 1e-4
   small     one 32 x 32 pair (3 blobs), FP64, rel KKT 1e-6
@@ -74,6 +75,9 @@ def make_workload(name, pairs):
     if name == "pair128":
         return ([workloads.pair_medium("blobs")], 1e-4, hot.HOT_FP32_STREAM,
                 "one 128x128 pair, 5 Gaussian blobs + floor 1e-3")
+    if name == "pair64":
+        return ([workloads.pair_medium("blobs", n=64)], 1e-4, hot.HOT_FP32_STREAM,
+                "one 64x64 pair, 5 Gaussian blobs + floor 1e-3")
     if name == "pair128nu":
         return ([workloads.pair_medium("blobs")], 1e-4, hot.HOT_FP32_STREAM,
                 "one 128x128 pair, 5 Gaussian blobs + floor 1e-3, non-uniform bins "
@@ -270,6 +274,10 @@ def main():
                          "reductions; fp64: FP64 throughout)")
     ap.add_argument("--tol", type=float, default=None,
                     help="override the workload's relative KKT tolerance")
+    ap.add_argument("--admm", action="store_true",
+                    help="the generalized ADMM baseline (rho 1.7) instead of HOT")
+    ap.add_argument("--abs-kkt", action="store_true",
+                    help="stop on the absolute KKT residual ||R(w_bar)|| instead of the relative one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (torch copy_) 5 times, for scaling "
                          "hardware byte counters")
@@ -286,7 +294,8 @@ def main():
     from paper_2408_00598_amd import hot
 
     pairs, tol, prec, base = make_workload(args.workload, args.pairs)
-    default_run = args.prec is None and args.tol is None and not args.sigma_update
+    default_run = (args.prec is None and args.tol is None and not args.sigma_update
+                   and not args.admm and not args.abs_kkt)
     if args.prec is not None:
         prec = hot.HOT_FP32_STREAM if args.prec == "fp32" else hot.HOT_FP64
     if args.tol is not None:
@@ -297,6 +306,13 @@ def main():
     torch.cuda.synchronize()
     ctx = hot.Context(0)
     flags = hot.HOT_FLAG_RESTART | (hot.HOT_FLAG_SIGMA_UPDATE if args.sigma_update else 0)
+    if args.admm:
+        flags = hot.HOT_FLAG_ADMM  # (relax <= 0 selects rho = 1.7)
+    if args.abs_kkt:
+        flags |= hot.HOT_FLAG_ABS_KKT
+        desc = desc.replace("rel KKT", "abs KKT")
+    if args.admm:
+        desc += ", generalized ADMM (rho 1.7)"
     kw = dict(tol=tol, max_iter=1000000, prec=prec, flags=flags)
     if args.workload == "pair128nu":  # grid-line positions of the non-uniform bins
         from paper_2408_00598_amd import workloads
@@ -374,6 +390,8 @@ def main():
         "roofline": roofline,
         "solve_stats": {"iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
                         "kkt_max": float(max(r["kkt"] for r in results)),
+                        "kkt_abs_max": float(max(r["kkt_abs"] for r in results)),
+                        "restarts_mean": float(np.mean([r["restarts"] for r in results])),
                         "converged": int(sum(r["status"] == 0 for r in results))},
     }
     if plan_stats:
