@@ -62,6 +62,33 @@ __device__ inline double chunk_sum(const double* __restrict__ p, int nchunk, int
   return (a0 + a1) + (a2 + a3);
 }
 
+// chunk_sum of two columns at once (q is read only when `two`): the same
+// order per column, twice the loads in flight
+__device__ inline void chunk_sum2(const double* __restrict__ p, const double* __restrict__ q,
+                                  bool two, int nchunk, int64_t stride, double& s0,
+                                  double& s1) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+  int c = 0;
+  for (; c + 4 <= nchunk; c += 4) {
+    a0 += p[(int64_t)c * stride];
+    a1 += p[(int64_t)(c + 1) * stride];
+    a2 += p[(int64_t)(c + 2) * stride];
+    a3 += p[(int64_t)(c + 3) * stride];
+    if (two) {
+      b0 += q[(int64_t)c * stride];
+      b1 += q[(int64_t)(c + 1) * stride];
+      b2 += q[(int64_t)(c + 2) * stride];
+      b3 += q[(int64_t)(c + 3) * stride];
+    }
+  }
+  for (; c < nchunk; ++c) {
+    a0 += p[(int64_t)c * stride];
+    if (two) b0 += q[(int64_t)c * stride];
+  }
+  s0 = (a0 + a1) + (a2 + a3);
+  s1 = (b0 + b1) + (b2 + b3);
+}
+
 // block-wide fixed-order totals of q values held by lane 0 of each wave
 __device__ inline double wave4(const double (&w)[4][kKP], int q) {
   return (w[0][q] + w[1][q]) + (w[2][q] + w[3][q]);
@@ -162,12 +189,18 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       double* R2 = arr + arr_R2(G);
       double sr2 = 0.0, t1 = 0.0;
       const double* cpj = colpart + F1.cpoff + (int64_t)j * F1.nchunk * m;
-      for (int i = tid; i < m; i += nthr) {
-        const double cs = chunk_sum(cpj + i, F1.nchunk, m);
-        const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs - fam_cr(ab, F1, i));
-        R2[(int64_t)j * m + i] = r2;
-        sr2 += r2;
-        t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
+      // columns tid, tid + nthr, ... in that order, two per step
+      for (int i0 = tid; i0 < m; i0 += 2 * nthr) {
+        double cs[2];
+        chunk_sum2(cpj + i0, cpj + i0 + nthr, i0 + nthr < m, F1.nchunk, m, cs[0], cs[1]);
+        for (int h = 0; h < 2; ++h) {
+          const int i = i0 + h * nthr;
+          if (i >= m) break;
+          const double r2 = mu1T[(int64_t)j * m + i] * isg - (cs[h] - fam_cr(ab, F1, i));
+          R2[(int64_t)j * m + i] = r2;
+          sr2 += r2;
+          t1 += rowsum[F1.rsoff + (int64_t)j * m + i];  // row j of the F1 row sums
+        }
       }
       sr2 = slab_sum(sr2);
       t1 = slab_sum(t1);
@@ -181,15 +214,19 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
       double* R3T = arr + arr_R3T(G);
       double s3 = 0.0, t2 = 0.0;
       const double* cpk = colpart + F2.cpoff + (int64_t)k * F2.nchunk * n;
-      for (int l = tid; l < n; l += nthr) {
-        double r3 = 0.0;
-        if (!(k == m - 1 && l == n - 1)) {
-          const double cs = chunk_sum(cpk + l, F2.nchunk, n);
-          r3 = mu2[(int64_t)k * n + l] * isg - (cs - fam_cr(ab, F2, l));
+      for (int l0 = tid; l0 < n; l0 += 2 * nthr) {
+        double cs[2];
+        chunk_sum2(cpk + l0, cpk + l0 + nthr, l0 + nthr < n, F2.nchunk, n, cs[0], cs[1]);
+        for (int h = 0; h < 2; ++h) {
+          const int l = l0 + h * nthr;
+          if (l >= n) break;
+          double r3 = 0.0;
+          if (!(k == m - 1 && l == n - 1))
+            r3 = mu2[(int64_t)k * n + l] * isg - (cs[h] - fam_cr(ab, F2, l));
+          R3T[(int64_t)k * n + l] = r3;
+          s3 += r3;
+          t2 += rowsum[F2.rsoff + (int64_t)k * n + l];  // row k of the F2 row sums
         }
-        R3T[(int64_t)k * n + l] = r3;
-        s3 += r3;
-        t2 += rowsum[F2.rsoff + (int64_t)k * n + l];  // row k of the F2 row sums
       }
       s3 = slab_sum(s3);
       t2 = slab_sum(t2);
