@@ -212,7 +212,9 @@ void hot_solution_free(hot_solution *sol);
  * (host, 4 doubles, nullable): L1 errors of row and column marginals before
  * repair, then after repair.  Entries of bin (k,j) are contiguous, ordered
  * by (k*n + j), then by source row i, then by target column l; the repair
- * entries follow. */
+ * entries follow.  Scratch (about 16 bytes per flow element) comes from a
+ * buffer the context keeps at the largest size a recovery has needed, until
+ * hot_ctx_destroy; recoveries on one context run one at a time. */
 hot_status hot_recover_plan(hot_ctx *ctx, const hot_solution *sol,
                             hot_stream_t stream, int32_t *src, int32_t *dst,
                             double *mass, int64_t capacity, int64_t *nnz,

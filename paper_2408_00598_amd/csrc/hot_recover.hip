@@ -449,20 +449,35 @@ void sum_into(const double* in, int64_t n, double* part, double* out, hipStream_
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, st, part, nb, out);
 }
 
-struct DevBuf {
-  std::vector<void*> ptrs;
-  ~DevBuf() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
+// Carves the recovery buffers out of the context's scratch (256-byte
+// aligned), growing it when this recovery needs more.  The caller holds
+// ctx->rec_mu.
+struct ScratchCarver {
+  hot_ctx* ctx;
+  std::vector<std::pair<void**, size_t>> want;
   template <typename X>
-  bool get(X** p, size_t count) {
-    void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(count * sizeof(X), 256)) != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
+  void add(X** p, size_t count) {
+    want.push_back({(void**)p, (std::max<size_t>(count * sizeof(X), 256) + 255) & ~size_t(255)});
+  }
+  bool commit() {
+    size_t need = 0;
+    for (const auto& w : want) need += w.second;
+    if (need > ctx->rec_bytes) {
+      if (ctx->rec_buf) (void)hipFree(ctx->rec_buf);
+      ctx->rec_buf = nullptr;
+      ctx->rec_bytes = 0;
+      if (hipMalloc(&ctx->rec_buf, need) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->rec_buf = nullptr;
+        return false;
+      }
+      ctx->rec_bytes = need;
     }
-    ptrs.push_back(q);
-    *p = (X*)q;
+    char* base = (char*)ctx->rec_buf;
+    for (const auto& w : want) {
+      *w.first = base;
+      base += w.second;
+    }
     return true;
   }
 };
@@ -491,15 +506,17 @@ extern "C" hot_status hot_recover_plan(hot_ctx* ctx, const hot_solution* sol, ho
   const double* mu1T = ws.arr + arr_mu1T(g);
   const double* mu2 = ws.arr + arr_mu2(g);
   hipStream_t st = (hipStream_t)stream;
-  DevBuf B;
+  std::lock_guard<std::mutex> rec_lock(ctx->rec_mu);  // the scratch is the context's
   double *w, *mt, *sums, *sums2, *rho_r, *rho_c, *err, *er, *ec, *Er, *Ec, *fb, *part, *res;
   long long *counts, *offs, *ncounts, *noffs, *ibsum;
   const int64_t nbs = (std::max(N, M) + kScanBlock - 1) / kScanBlock + 2;
-  if (!B.get(&w, N) || !B.get(&mt, N) || !B.get(&sums, 2 * M) || !B.get(&sums2, 2 * M) ||
-      !B.get(&rho_r, M) || !B.get(&rho_c, M) || !B.get(&err, M) || !B.get(&er, M) ||
-      !B.get(&ec, M) || !B.get(&Er, M + 1) || !B.get(&Ec, M + 1) || !B.get(&fb, nbs) ||
-      !B.get(&part, nbs) || !B.get(&res, 8) || !B.get(&counts, M) || !B.get(&offs, M + 1) ||
-      !B.get(&ncounts, M) || !B.get(&noffs, M + 1) || !B.get(&ibsum, nbs)) {
+  ScratchCarver B{ctx, {}};
+  B.add(&w, N); B.add(&mt, N); B.add(&sums, 2 * M); B.add(&sums2, 2 * M);
+  B.add(&rho_r, M); B.add(&rho_c, M); B.add(&err, M); B.add(&er, M); B.add(&ec, M);
+  B.add(&Er, M + 1); B.add(&Ec, M + 1); B.add(&fb, nbs); B.add(&part, nbs); B.add(&res, 8);
+  B.add(&counts, M); B.add(&offs, M + 1); B.add(&ncounts, M); B.add(&noffs, M + 1);
+  B.add(&ibsum, nbs);
+  if (!B.commit()) {
     ctx->err = "recovery workspace allocation failed";
     return HOT_E_NOMEM;
   }

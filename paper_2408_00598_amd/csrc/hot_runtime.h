@@ -195,6 +195,14 @@ struct hot_ctx {
   // measurement counters (hot_ctx_profile_read)
   bool profiling = false;
   double prof_seconds = 0, prof_launches = 0, prof_bytes = 0, iters_launched = 0;
+  // plan-recovery scratch: grows to the largest recovery seen, kept until the
+  // context is destroyed; rec_mu is held for the whole of a recovery
+  std::mutex rec_mu;
+  void* rec_buf = nullptr;
+  size_t rec_bytes = 0;
+  ~hot_ctx() {
+    if (rec_buf) (void)hipFree(rec_buf);
+  }
 };
 
 struct hot_solution {
