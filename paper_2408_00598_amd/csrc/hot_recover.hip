@@ -125,6 +125,16 @@ __device__ inline int first_above(const double* Q, int n, double v) {
   return lo;
 }
 
+// smallest index l in [0, n] with l == n or Q[l] >= v (Q nondecreasing)
+__device__ inline int count_below(const double* Q, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (Q[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 enum RecPass { PASS_COUNT = 0, PASS_COLSCALED = 1, PASS_BOTHSCALED = 2, PASS_WRITE = 3 };
 
 // The bin's coupling entries in order, 64 candidates per call.  Candidate t
@@ -215,32 +225,41 @@ __global__ __launch_bounds__(64) void k_rec_bin(int m, int n, const double* __re
     for (int l = lane; l < n; l += 64) {
       const double lo = Q[l], hi = Q[l + 1];
       double acc = 0.0;
-      if (hi > lo)
-        for (int i = first_above(P, m, lo); i < m && P[i] < hi; ++i) {
+      if (hi > lo) {
+        const int i_end = count_below(P, m, hi);  // the overlaps form one run of sources
+#pragma unroll 4
+        for (int i = first_above(P, m, lo); i < i_end; ++i) {
           const double ov = fmin(P[i + 1], hi) - fmax(P[i], lo);
           if (ov > 0.0) acc += ov * R[i];
         }
+      }
       m2[l] = acc;
     }
   } else if (PASS == PASS_BOTHSCALED) {
     for (int i = lane; i < m; i += 64) {
       const double lo = P[i], hi = P[i + 1];
       double acc = 0.0;
-      if (hi > lo)
-        for (int l = first_above(Q, n, lo); l < n && Q[l] < hi; ++l) {
+      if (hi > lo) {
+        const int l_end = count_below(Q, n, hi);  // the overlaps form one run of targets
+#pragma unroll 4
+        for (int l = first_above(Q, n, lo); l < l_end; ++l) {
           const double ov = fmin(hi, Q[l + 1]) - fmax(lo, Q[l]);
           if (ov > 0.0) acc += ov * R[i] * C[l];
         }
+      }
       m1[i] = acc;
     }
     for (int l = lane; l < n; l += 64) {
       const double lo = Q[l], hi = Q[l + 1];
       double acc = 0.0;
-      if (hi > lo)
-        for (int i = first_above(P, m, lo); i < m && P[i] < hi; ++i) {
+      if (hi > lo) {
+        const int i_end = count_below(P, m, hi);  // the overlaps form one run of sources
+#pragma unroll 4
+        for (int i = first_above(P, m, lo); i < i_end; ++i) {
           const double ov = fmin(P[i + 1], hi) - fmax(P[i], lo);
           if (ov > 0.0) acc += ov * R[i] * C[l];
         }
+      }
       m2[l] = acc;
     }
   } else {  // PASS_WRITE: the entries in order, 64 candidates per step
