@@ -81,9 +81,9 @@ __device__ __forceinline__ void slab_rows(const SlabCtx& x, const T* __restrict_
       for (int v = 0; v < MAXVPL; ++v) {
         const int q0 = (x.lin + (v << x.lrs)) * W;
         if (v < x.vpl && rvv[u] && q0 < L) {
-          xs[u][v] = *reinterpret_cast<const VT*>(src + (int64_t)prow[u] * P + q0);
-          if (ANC == ANC_SEP) xa[u][v] = *reinterpret_cast<const VT*>(anc + (int64_t)prow[u] * P + q0);
-          if constexpr (RDX) xq[u][v] = *reinterpret_cast<const VT*>(xr + (int64_t)prow[u] * P + q0);
+          xs[u][v] = vload_nt<T>(src + (int64_t)prow[u] * P + q0);
+          if (ANC == ANC_SEP) xa[u][v] = vload_nt<T>(anc + (int64_t)prow[u] * P + q0);
+          if constexpr (RDX) xq[u][v] = vload_nt<T>(xr + (int64_t)prow[u] * P + q0);
         }
       }
     }
@@ -381,8 +381,8 @@ __device__ __forceinline__ void slab_wave(const SlabCtx& x, const T* __restrict_
       for (int v = 0; v < MAXVPL; ++v) {
         const int q0 = (x.lin + (v << x.lrs)) * W;
         if (v < x.vpl && rvv[u] && q0 < L) {
-          xs[u][v] = *reinterpret_cast<const VT*>(src + (int64_t)prow[u] * P + q0);
-          if (ANC == ANC_SEP) xa[u][v] = *reinterpret_cast<const VT*>(anc + (int64_t)prow[u] * P + q0);
+          xs[u][v] = vload_nt<T>(src + (int64_t)prow[u] * P + q0);
+          if (ANC == ANC_SEP) xa[u][v] = vload_nt<T>(anc + (int64_t)prow[u] * P + q0);
         }
       }
     }
