@@ -197,3 +197,47 @@ def test_batch_with_early_finishers_equals_alone():
         ra, _ = c.solve(a, b, tol=1e-6, max_iter=200000)
         for key in ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status"):
             assert ra[key] == rb[key], (key, ra[key], rb[key])
+
+
+def test_graph_replays_equal_direct_launches_bitwise(monkeypatch):
+    """Iterations run as captured graphs, replayed many times with host reads
+    of the control blocks and unrelated eager device work in between, give
+    the same results and states as the same iterations launched directly
+    (HOT_NO_GRAPH=1): batch and single-pair paths, both precisions, and a
+    second graph solve on the same context after eager work."""
+    need_gpu()
+    import torch
+    from paper_2408_00598_amd import hot, workloads
+    pairs = workloads.batch_pairs(24, sides=(16, 24, 32, 64, 96))
+    dp = [(dev(a), dev(b)) for a, b in pairs]
+    rng = np.random.default_rng(workloads.seed_for(1, 72))
+    a = dev(workloads.gaussian_blobs(72, 72, 3, rng))
+    b = dev(workloads.gaussian_blobs(72, 72, 3, rng))
+    monkeypatch.setenv("HOT_NO_GRAPH", "1")
+    direct = hot.Context(0)
+    monkeypatch.delenv("HOT_NO_GRAPH")
+    graph = hot.Context(0)
+    keys = ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status")
+    side = torch.arange(1 << 20, device="cuda:0", dtype=torch.float64)
+    for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
+        monkeypatch.setenv("HOT_NO_GRAPH", "1")
+        want = direct.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec)
+        rw, sw = direct.solve(a, b, keep=True, max_iter=300, prec=prec,
+                              flags=hot.HOT_FLAG_RESTART | hot.HOT_FLAG_FIXED_ITERS)
+        want_state = [t.cpu() for t in sw.export()]
+        monkeypatch.delenv("HOT_NO_GRAPH")
+        for rep in range(2):
+            got = graph.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec)
+            for ra, rb in zip(want, got):
+                assert rb["iters"] > 0
+                for key in keys:
+                    assert ra[key] == rb[key], (prec, rep, key, ra[key], rb[key])
+            rg, sg = graph.solve(a, b, keep=True, max_iter=300, prec=prec,
+                                 flags=hot.HOT_FLAG_RESTART | hot.HOT_FLAG_FIXED_ITERS)
+            for key in keys:
+                assert rw[key] == rg[key], (prec, rep, key, rw[key], rg[key])
+            for t0, t1 in zip(want_state, sg.export()):
+                assert torch.equal(t0, t1.cpu())
+            # eager device work and a synchronisation between the two rounds
+            assert float((side * 2.0).sum().item()) == float((1 << 20) * ((1 << 20) - 1))
+            torch.cuda.synchronize()
