@@ -99,6 +99,7 @@ Tuning default_tuning() {
   t.fuse = 1;
   t.row_group = 0;
   t.reduce_group = 0;
+  t.solve_pre = -1;
   return t;
 }
 
@@ -950,6 +951,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.reduce_group = std::max(0, std::min(16, std::atoi(e)));
   e = std::getenv("HOT_ROW_GROUP");
   if (e) c->tune.row_group = std::max(0, std::min(16, std::atoi(e)));
+  e = std::getenv("HOT_SOLVE_PRE");
+  if (e) c->tune.solve_pre = std::max(-1, std::min(1, std::atoi(e)));
   e = std::getenv("HOT_FUSE");
   if (e) c->tune.fuse = std::atoi(e) != 0;
   e = std::getenv("HOT_BATCH_GROUPS");
@@ -1043,6 +1046,7 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
   }
   ws->args.nt_store = ctx->tune.nt_store;
   ws->args.fuse = ctx->tune.fuse;
+  ws->args.solve_pre = ctx->tune.solve_pre;
   // the algorithmic byte count is kept only when the passes are timed
   ws->args.bytes_ctr = ws->profile ? ws->bytes_ctr : nullptr;
   if (s != HOT_OK) return s;

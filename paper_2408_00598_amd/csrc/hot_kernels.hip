@@ -527,27 +527,42 @@ __device__ inline SolveScalars solve_scalars(const PairGeo& G, const double* vec
   return S;
 }
 
-template <int FROM_R>
-__device__ inline double t_entry(const PairGeo& G, const double* vec, const double* ab,
-                                 const SolveScalars& S,
-                                 int k) {
-  const double dm = (double)G.m;
-  const double d = dinv(G.m, k);
-  return (Sp_of<FROM_R>(G, vec, ab, k) - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
-}
+// Inputs of a solve block that do not depend on the solve scalars, read
+// before wave 0 has rebuilt them: for the first beta slab of a wave, the
+// slab's scalar term without the scalar parts (F1: b1_j - a_j, so that
+// rs_j = base + sp / n + 1^T Q t; F2: Sp_k, so that t_k = (base - sa / m) d_k
+// + m (m+1) u d_k) and the lane's first two R2 / R3^T entries.
+struct BetaPre {
+  double base;
+  double r0, r1;
+};
 
-// 1^T (Rhat1^j + Q t)
 template <int FROM_R>
-__device__ inline double rs_of(const PairGeo& G, const double* vec, const double* ab,
-                               const SolveScalars& S, int j) {
-  return b1_of<FROM_R>(G, vec, ab, j) - vec[vec_a(G) + j] + S.sp / (double)G.n + S.sq;
+__device__ __forceinline__ BetaPre beta_prefetch(const PairGeo& G, int slab, const double* arr,
+                                        const double* vec, const double* ab, int lane) {
+  BetaPre P{0.0, 0.0, 0.0};
+  const int m = G.m, n = G.n;
+  if (slab < n) {
+    P.base = b1_of<FROM_R>(G, vec, ab, slab) - vec[vec_a(G) + slab];
+    const double* R2 = arr + arr_R2(G) + (int64_t)slab * m;
+    if (lane < m) P.r0 = R2[lane];
+    if (lane + 64 < m) P.r1 = R2[lane + 64];
+  } else if (slab < n + m) {
+    const int k = slab - n;
+    P.base = Sp_of<FROM_R>(G, vec, ab, k);
+    const double* R3T = arr + arr_R3T(G) + (int64_t)k * n;
+    if (lane < n) P.r0 = R3T[lane];
+    if (lane + 64 < n) P.r1 = R3T[lane + 64];
+  }
+  return P;
 }
 
 // beta of one slab, and the slab's (sum alpha, sum beta): sum_k y1[j][k] =
 // rs_j / n and sum_j y1[j][k] = t[k] in closed form.
 template <int FROM_R>
-__device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const double* vec,
-                           double* ab, const SolveScalars& S, int lane) {
+__device__ __forceinline__ void solve_beta(const PairGeo& G, int slab, const double* arr,
+                                           double* ab, const SolveScalars& S, int lane,
+                                           const BetaPre P) {
   const int m = G.m, n = G.n;
   const double dm = (double)m, dn = (double)n;
   if (slab < n) {  // F1^(j): beta = y2[j][.]
@@ -555,10 +570,11 @@ __device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const 
     const double* R2 = arr + arr_R2(G);
     const FamGeo F = G.f[0];
     double* be = ab + F.aboff + (int64_t)j * 2 * m + m;
-    const double rsj = rs_of<FROM_R>(G, vec, ab, S, j);
+    const double rsj = P.base + S.sp / dn + S.sq;
     double sb = 0.0;
-    for (int i = lane; i < m; i += 64) {
-      const double v = (R2[(int64_t)j * m + i] - rsj / dn) / dm;
+    for (int i = lane, it = 0; i < m; i += 64, ++it) {
+      const double r = it == 0 ? P.r0 : (it == 1 ? P.r1 : R2[(int64_t)j * m + i]);
+      const double v = (r - rsj / dn) / dm;
       be[i] = v;
       sb += v;
     }
@@ -572,10 +588,12 @@ __device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const 
     const double* R3T = arr + arr_R3T(G);
     const FamGeo F = G.f[1];
     double* be = ab + F.aboff + (int64_t)k * 2 * n + n;
-    const double tk = t_entry<FROM_R>(G, vec, ab, S, k);
+    const double d = dinv(m, k);
+    const double tk = (P.base - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
     double sb = 0.0;
-    for (int l = lane; l < n; l += 64) {
-      const double v = (k == m - 1 && l == n - 1) ? 0.0 : (R3T[(int64_t)k * n + l] + tk) / dn;
+    for (int l = lane, it = 0; l < n; l += 64, ++it) {
+      const double r = it == 0 ? P.r0 : (it == 1 ? P.r1 : R3T[(int64_t)k * n + l]);
+      const double v = (k == m - 1 && l == n - 1) ? 0.0 : (r + tk) / dn;
       be[l] = v;
       sb += v;
     }
@@ -587,71 +605,120 @@ __device__ void solve_beta(const PairGeo& G, int slab, const double* arr, const 
   }
 }
 
-// y1 on a 32 x 32 tile.  R1[j][k] comes from the two row-sum arrays (or is
-// read directly for FROM_R).
+// y1 on a 32 x 32 tile of (j, k), in three parts around the decision:
+//   tile_stage (waves 1-3, before it): R1 (or the F1 / F2 row sums) into LDS;
+//   tile_pre / tile_scalars (wave 0, its lanes 0-31 for rows j and 32-63 for
+//     columns k): the S-free row / column terms, loaded before the decision
+//     and completed with the solve scalars after it;
+//   solve_alpha_tile (every thread, after the barrier): y1, written as alpha
+//     of F1^(j) (row j) and, transposed through LDS, as -alpha of F2^(k).
+struct TileLds {
+  double T1[32][33], T2[32][33];  // T1 holds R1 (or rs1) and then, in place, y1
+  double rs[32], a[32], cn[32], qt[32], p3[32], cm[32];
+};
+
+struct TilePre {
+  double base, x, y;  // rows: b1_j - a_j, a_j, C_n(j); columns: Sp_k, PR3_k, C_m(k)
+};
+
 template <int FROM_R>
-__device__ void solve_alpha_tile(const PairGeo& G, int tile, const double* rowsum,
-                                 const double* arr, const double* vec, double* ab,
-                                 const SolveScalars& S) {
-  // T1 holds R1 (or the F1 row sums) and then, in place, y1 of the tile
-  __shared__ double T1[32][33], T2[32][33];
-  __shared__ double s_rs[32], s_a[32], s_cn[32], s_qt[32], s_p3[32], s_cm[32];
+__device__ __forceinline__ void tile_stage(const PairGeo& G, int tile, const double* rowsum,
+                                  const double* arr, TileLds& L, int t0, int tstep) {
   const int m = G.m, n = G.n;
-  const double dm = (double)m, dn = (double)n;
-  const int jt = tile % G.ntj, kt = tile / G.ntj;
-  const int j0 = 32 * jt, k0 = 32 * kt;
-  const int t = threadIdx.x;
-  const FamGeo F1 = G.f[0], F2 = G.f[1];
-  if (t < 32) {
-    const int j = j0 + t;
-    if (j < n) {
-      s_rs[t] = rs_of<FROM_R>(G, vec, ab, S, j);
-      s_a[t] = vec[vec_a(G) + j];
-      s_cn[t] = fam_cr(ab, F2, j);
-    }
-  } else if (t < 64) {
-    const int kk = t - 32, k = k0 + kk;
-    if (k < m) {
-      const double tk = t_entry<FROM_R>(G, vec, ab, S, k);
-      s_qt[kk] = (k == m - 1) ? tk - tk / dn : tk;
-      s_p3[kk] = vec[vec_PR3(G) + k];
-      s_cm[kk] = fam_cr(ab, F1, k);
-    }
-  }
-  const double* rs1 = rowsum + F1.rsoff;  // [n][m]
-  const double* rs2 = rowsum + F2.rsoff;  // [m][n]
+  const int j0 = 32 * (tile % G.ntj), k0 = 32 * (tile / G.ntj);
+  const double* rs1 = rowsum + G.f[0].rsoff;  // [n][m]
+  const double* rs2 = rowsum + G.f[1].rsoff;  // [m][n]
   const double* R1 = arr + arr_R1(G);
-  for (int e = t; e < 1024; e += kWG) {
+  for (int e = t0; e < 1024; e += tstep) {
     const int r = e >> 5, c = e & 31;
     const int j = j0 + r, k = k0 + c;        // T1[r][c] = (j, k)
-    T1[r][c] = (j < n && k < m) ? (FROM_R ? R1[(int64_t)j * m + k] : rs1[(int64_t)j * m + k]) : 0.0;
+    L.T1[r][c] = (j < n && k < m) ? (FROM_R ? R1[(int64_t)j * m + k] : rs1[(int64_t)j * m + k]) : 0.0;
     if (!FROM_R) {
       const int k2 = k0 + r, j2 = j0 + c;    // T2[r][c] = rs2[k2][j2]
-      T2[r][c] = (k2 < m && j2 < n) ? rs2[(int64_t)k2 * n + j2] : 0.0;
+      L.T2[r][c] = (k2 < m && j2 < n) ? rs2[(int64_t)k2 * n + j2] : 0.0;
     }
   }
-  __syncthreads();
+}
+
+template <int FROM_R>
+__device__ __forceinline__ TilePre tile_pre(const PairGeo& G, int tile, const double* vec,
+                                   const double* ab, int t) {
+  TilePre P{0.0, 0.0, 0.0};
+  const int j0 = 32 * (tile % G.ntj), k0 = 32 * (tile / G.ntj);
+  if (t < 32) {
+    const int j = j0 + t;
+    if (j < G.n) {
+      P.x = vec[vec_a(G) + j];
+      P.base = b1_of<FROM_R>(G, vec, ab, j) - P.x;
+      P.y = fam_cr(ab, G.f[1], j);
+    }
+  } else {
+    const int k = k0 + t - 32;
+    if (k < G.m) {
+      P.base = Sp_of<FROM_R>(G, vec, ab, k);
+      P.x = vec[vec_PR3(G) + k];
+      P.y = fam_cr(ab, G.f[0], k);
+    }
+  }
+  return P;
+}
+
+__device__ __forceinline__ void tile_scalars(const PairGeo& G, int tile, const TilePre P,
+                                    const SolveScalars& S, TileLds& L, int t) {
+  const double dm = (double)G.m, dn = (double)G.n;
+  const int j0 = 32 * (tile % G.ntj), k0 = 32 * (tile / G.ntj);
+  if (t < 32) {
+    if (j0 + t < G.n) {
+      L.rs[t] = P.base + S.sp / dn + S.sq;
+      L.a[t] = P.x;
+      L.cn[t] = P.y;
+    }
+  } else {
+    const int kk = t - 32, k = k0 + kk;
+    if (k < G.m) {
+      const double d = dinv(G.m, k);
+      const double tk = (P.base - S.sa / dm) * d + dm * (dm + 1.0) * S.u * d;
+      L.qt[kk] = (k == G.m - 1) ? tk - tk / dn : tk;
+      L.p3[kk] = P.x;
+      L.cm[kk] = P.y;
+    }
+  }
+}
+
+template <int FROM_R>
+__device__ __forceinline__ void solve_alpha_tile(const PairGeo& G, int tile, double* ab,
+                                                 TileLds& L) {
+  const int m = G.m, n = G.n;
+  const double dm = (double)m, dn = (double)n;
+  const int j0 = 32 * (tile % G.ntj), k0 = 32 * (tile / G.ntj);
+  const int t = threadIdx.x;
+  const FamGeo F1 = G.f[0], F2 = G.f[1];
   for (int e = t; e < 1024; e += kWG) {
     const int jj = e >> 5, kk = e & 31;
     const int j = j0 + jj, k = k0 + kk;
     if (j < n && k < m) {
       const double r1 =
-          FROM_R ? T1[jj][kk] : -(T1[jj][kk] - s_cm[kk]) + (T2[kk][jj] - s_cn[jj]);
-      const double rh = r1 - s_a[jj] / dm + s_p3[kk] / dn;
-      const double y = (rh + s_qt[kk] + s_rs[jj] / dn) / (dm + dn);
+          FROM_R ? L.T1[jj][kk] : -(L.T1[jj][kk] - L.cm[kk]) + (L.T2[kk][jj] - L.cn[jj]);
+      const double rh = r1 - L.a[jj] / dm + L.p3[kk] / dn;
+      const double y = (rh + L.qt[kk] + L.rs[jj] / dn) / (dm + dn);
       ab[F1.aboff + (int64_t)j * 2 * m + k] = y;
-      T1[jj][kk] = y;  // (this thread alone read T1[jj][kk] above)
+      L.T1[jj][kk] = y;  // (this thread alone read T1[jj][kk] above)
     }
   }
   __syncthreads();
   for (int e = t; e < 1024; e += kWG) {
     const int kk = e >> 5, jj = e & 31;
     const int j = j0 + jj, k = k0 + kk;
-    if (j < n && k < m) ab[F2.aboff + (int64_t)k * 2 * n + j] = -T1[jj][kk];
+    if (j < n && k < m) ab[F2.aboff + (int64_t)k * 2 * n + j] = -L.T1[jj][kk];
   }
 }
 
-template <int FROM_R>
+// PRE = 1 (launches of few blocks, where the solve is latency-bound): the
+// loads that need no decision go out before it (wasted only on the pass that
+// stops the pair), waves 1-3 staging the tile while wave 0 decides.  PRE = 0
+// (large launches, where occupancy matters more: the early loads hold
+// registers across the decision) issues them after it.  Same arithmetic.
+template <int FROM_R, int PRE>
 __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ sblocks,
                                                     const PairGeo* __restrict__ geo,
                                                     const PairCtl* __restrict__ ctl,
@@ -663,6 +730,7 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
   __shared__ PairCtl s_nx;
   __shared__ SolveScalars s_S;
   __shared__ int s_solve;
+  __shared__ TileLds s_tile;
   const PBlock pbk = sblocks[blockIdx.x];
   const bool head = (pbk.kind == 0 && pbk.blk == 0 && threadIdx.x == 0);
   if (!FROM_R) {
@@ -673,18 +741,35 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
     }
   }
   const PairGeo G = geo[pbk.pair];
-  if (threadIdx.x < 64) {  // wave 0 decides and rebuilds the solve scalars
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // (kind 1, wave 0: holds the tile's row / column terms as base, r0, r1)
+  BetaPre bp{0.0, 0.0, 0.0};
+  if constexpr (PRE) {
+    if (pbk.kind == 0) {
+      bp = beta_prefetch<FROM_R>(G, 4 * G.spw * pbk.blk + wave, arr, vec, ab, lane);
+    } else if (wave == 0) {
+      const TilePre tp = tile_pre<FROM_R>(G, pbk.blk, vec, ab, lane);
+      bp = BetaPre{tp.base, tp.x, tp.y};
+    } else {
+      tile_stage<FROM_R>(G, pbk.blk, rowsum, arr, s_tile, threadIdx.x - 64, kWG - 64);
+    }
+  }
+  if (wave == 0) {  // wave 0 decides and rebuilds the solve scalars
     bool solve = true;
     PairCtl nx;
     if (!FROM_R) {
       const PairCtl c = ctl[pbk.pair];
       double acc[kNKP];
-      if (c.mode == MODE_CHECK) reduce_kpart(G, vec, threadIdx.x, acc);
+      if (c.mode == MODE_CHECK) reduce_kpart(G, vec, lane, acc);
       decide(G, c, acc, nx, solve);
     }
     SolveScalars S;
-    if (solve) S = solve_scalars<FROM_R>(G, vec, ab, threadIdx.x);
-    if (threadIdx.x == 0) {
+    if (solve) {
+      S = solve_scalars<FROM_R>(G, vec, ab, lane);
+      if (PRE && pbk.kind != 0)
+        tile_scalars(G, pbk.blk, TilePre{bp.base, bp.r0, bp.r1}, S, s_tile, lane);
+    }
+    if (lane == 0) {
       if (!FROM_R) s_nx = nx;
       s_solve = solve ? 1 : 0;
       if (solve) s_S = S;
@@ -692,12 +777,24 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
   }
   __syncthreads();
   if (s_solve) {
-    if (pbk.kind == 0)
-      for (int q = 0; q < G.spw; ++q)  // slabs 4 (spw b + q) + w
-        solve_beta<FROM_R>(G, 4 * (G.spw * pbk.blk + q) + (threadIdx.x >> 6), arr, vec, ab, s_S,
-                           threadIdx.x & 63);
-    else
-      solve_alpha_tile<FROM_R>(G, pbk.blk, rowsum, arr, vec, ab, s_S);
+    if (pbk.kind == 0) {
+      for (int q = 0; q < G.spw; ++q) {  // slabs 4 (spw b + q) + w
+        const int slab = 4 * (G.spw * pbk.blk + q) + wave;
+        const BetaPre P =
+            (PRE && q == 0) ? bp : beta_prefetch<FROM_R>(G, slab, arr, vec, ab, lane);
+        solve_beta<FROM_R>(G, slab, arr, ab, s_S, lane, P);
+      }
+    } else {
+      if constexpr (!PRE) {
+        if (wave == 0) {
+          const TilePre tp = tile_pre<FROM_R>(G, pbk.blk, vec, ab, lane);
+          tile_scalars(G, pbk.blk, tp, s_S, s_tile, lane);
+        }
+        tile_stage<FROM_R>(G, pbk.blk, rowsum, arr, s_tile, threadIdx.x, kWG);
+        __syncthreads();
+      }
+      solve_alpha_tile<FROM_R>(G, pbk.blk, ab, s_tile);
+    }
   }
   if (!FROM_R && head) ctl_next[pbk.pair] = s_nx;
 }
@@ -910,13 +1007,25 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 // Host-side launchers (C++ linkage inside the library).
 // ---------------------------------------------------------------------------
 
+template <int FROM_R>
+static void launch_solve(const LaunchArgs& a, const PairCtl* ctl, PairCtl* ctl_next,
+                         const double* rowsum, hipStream_t st) {
+  // by launch size: at most four blocks per CU (256 CUs), the solve is
+  // latency-bound and the early loads pay
+  if (a.solve_pre > 0 || (a.solve_pre < 0 && a.nsblocks <= 1024))
+    hipLaunchKernelGGL((k_pair_solve<FROM_R, 1>), dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks,
+                       a.geo, ctl, ctl_next, rowsum, a.arr, a.vec, a.ab);
+  else
+    hipLaunchKernelGGL((k_pair_solve<FROM_R, 0>), dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks,
+                       a.geo, ctl, ctl_next, rowsum, a.arr, a.vec, a.ab);
+}
+
 void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
                      a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec, a.bytes_ctr,
                      a.fp32 ? 4 : 8);
-  hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
-                     a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
+  launch_solve<0>(a, a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], st);
 }
 
 // One iteration: slab pass, pair reduce, pair solve.  Reads ctl[par], writes ctl[1-par].
@@ -926,8 +1035,7 @@ void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
                      a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec, a.bytes_ctr,
                      a.fp32 ? 4 : 8);
-  hipLaunchKernelGGL(k_pair_solve<0>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
-                     a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], a.arr, a.vec, a.ab);
+  launch_solve<0>(a, a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], st);
 }
 
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
@@ -966,9 +1074,7 @@ void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
   hipLaunchKernelGGL(k_scatter_R, dim3(grid), dim3(kWG), 0, st, a.geo, pair, R, a.arr);
   hipLaunchKernelGGL(k_pair_sums_from_R, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.arr, a.vec);
-  hipLaunchKernelGGL(k_pair_solve<1>, dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks, a.geo,
-                     (const PairCtl*)nullptr, (PairCtl*)nullptr, (const double*)nullptr, a.arr,
-                     a.vec, a.ab);
+  launch_solve<1>(a, nullptr, nullptr, nullptr, st);
 }
 
 }  // namespace hot

@@ -241,3 +241,38 @@ def test_graph_replays_equal_direct_launches_bitwise(monkeypatch):
             # eager device work and a synchronisation between the two rounds
             assert float((side * 2.0).sum().item()) == float((1 << 20) * ((1 << 20) - 1))
             torch.cuda.synchronize()
+
+
+def test_solve_load_order_bitwise(monkeypatch):
+    """The solve issuing its decision-free loads before the decision
+    (HOT_SOLVE_PRE=1) or after it (0) computes the same values: identical
+    results and states, batch (tiles and several slabs per wave) and a
+    rectangular single pair, both precisions."""
+    need_gpu()
+    import torch
+    from paper_2408_00598_amd import hot, workloads
+    pairs = workloads.batch_pairs(20, sides=(8, 24, 40, 72, 130))
+    dp = [(dev(a), dev(b)) for a, b in pairs]
+    rng = np.random.default_rng(workloads.seed_for(2, 70))
+    a = rng.uniform(0.05, 1, (70, 45)); a /= a.sum()
+    b = rng.uniform(0.05, 1, (70, 45)); b /= b.sum()
+    a, b = dev(a), dev(b)
+    ctxs = []
+    for pre in ("0", "1"):
+        monkeypatch.setenv("HOT_SOLVE_PRE", pre)
+        ctxs.append(hot.Context(0))
+    keys = ("primal_obj", "dual_obj", "kkt", "iters", "restarts", "status")
+    for prec in (hot.HOT_FP64, hot.HOT_FP32_STREAM):
+        rs = [c.batch_solve(dp, tol=1e-5, max_iter=200000, prec=prec) for c in ctxs]
+        for ra, rb in zip(*rs):
+            for key in keys:
+                assert ra[key] == rb[key], (prec, key, ra[key], rb[key])
+        outs = []
+        for c in ctxs:
+            r, sol = c.solve(a, b, keep=True, max_iter=151, prec=prec,
+                             flags=hot.HOT_FLAG_RESTART | hot.HOT_FLAG_FIXED_ITERS)
+            outs.append((r, [t.cpu() for t in sol.export()]))
+        for key in keys:
+            assert outs[0][0][key] == outs[1][0][key], (prec, key)
+        for t0, t1 in zip(outs[0][1], outs[1][1]):
+            assert torch.equal(t0, t1)
