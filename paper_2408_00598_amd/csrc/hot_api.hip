@@ -1271,6 +1271,7 @@ hot_status hot_aat_solve(hot_ctx* ctx, int32_t m, int32_t n, const double* R, do
   }
   hot_status s = ws->alloc_all(ctx);
   if (s != HOT_OK) return s;
+  ws->args.solve_pre = ctx->tune.solve_pre;
   hipStream_t st = (hipStream_t)stream;
   HIPCK(hipMemcpyAsync(ws->geo_d, ws->lay.geo.data(), sizeof(PairGeo), hipMemcpyHostToDevice, st));
   HIPCK(hipMemcpyAsync(ws->blocks_d, ws->lay.blocks.data(), ws->lay.blocks.size() * sizeof(PBlock),

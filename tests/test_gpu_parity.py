@@ -40,6 +40,23 @@ def test_aat_solve_matches_oracle(oracle, m, n):
     assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(R) * (m + n)
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (7, 5), (64, 48), (100, 3)])
+def test_aat_solve_both_load_orders(monkeypatch, oracle, m, n):
+    """The solve with its decision-free loads after (HOT_SOLVE_PRE=0) and
+    before (1) the scalar rebuild: the same y, bit for bit, and the oracle's."""
+    need_gpu()
+    import torch
+    from paper_2408_00598_amd import hot
+    rng = np.random.default_rng(m * 1000 + n + 7)
+    R = dev(rng.standard_normal(3 * m * n - 1))
+    ys = []
+    for pre in ("0", "1"):
+        monkeypatch.setenv("HOT_SOLVE_PRE", pre)
+        ys.append(hot.Context(0).aat_solve(m, n, R).cpu())
+    assert torch.equal(ys[0], ys[1])
+    assert rel(ys[0].numpy(), oracle.solve_aat(m, n, R.cpu().numpy())) <= 1e-12
+
+
 @pytest.mark.parametrize("m,n", SHAPES)
 @pytest.mark.parametrize("k", [1, 10, 100])
 def test_fixed_iteration_trajectory_fp64(oracle, m, n, k):
