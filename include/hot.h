@@ -131,8 +131,8 @@ typedef struct hot_server hot_server;
  * HOT_FUSE (0: separate plain and check/restart slab kernels),
  * HOT_ROW_GROUP (slabs per solve wave; results unchanged), HOT_REDUCE_GROUP
  * (row slots per reduce workgroup; results unchanged), HOT_BATCH_GROUPS (1..4
- * concurrent groups of a batch), HOT_SOLVE_PRE (-1: by launch size, 0/1: the
- * solve issues its decision-free loads after / before the decision; results
+ * concurrent groups of a batch), HOT_SOLVE_PRE (1, the default / 0: the solve
+ * issues its decision-free loads before / after the decision; results
  * unchanged).
  * HOT_NO_GRAPH=1 launches every iteration directly instead of through
  * captured graphs. */

@@ -99,7 +99,7 @@ Tuning default_tuning() {
   t.fuse = 1;
   t.row_group = 0;
   t.reduce_group = 0;
-  t.solve_pre = -1;
+  t.solve_pre = 1;
   return t;
 }
 
@@ -952,7 +952,7 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   e = std::getenv("HOT_ROW_GROUP");
   if (e) c->tune.row_group = std::max(0, std::min(16, std::atoi(e)));
   e = std::getenv("HOT_SOLVE_PRE");
-  if (e) c->tune.solve_pre = std::max(-1, std::min(1, std::atoi(e)));
+  if (e) c->tune.solve_pre = std::atoi(e) != 0;
   e = std::getenv("HOT_FUSE");
   if (e) c->tune.fuse = std::atoi(e) != 0;
   e = std::getenv("HOT_BATCH_GROUPS");

@@ -713,11 +713,10 @@ __device__ __forceinline__ void solve_alpha_tile(const PairGeo& G, int tile, dou
   }
 }
 
-// PRE = 1 (launches of few blocks, where the solve is latency-bound): the
-// loads that need no decision go out before it (wasted only on the pass that
-// stops the pair), waves 1-3 staging the tile while wave 0 decides.  PRE = 0
-// (large launches, where occupancy matters more: the early loads hold
-// registers across the decision) issues them after it.  Same arithmetic.
+// PRE = 1 (the default): the loads that need no decision go out before it
+// (wasted only on the pass that stops the pair), waves 1-3 staging the tile
+// while wave 0 decides.  PRE = 0 issues them after it (fewer registers held
+// across the decision: 69 against 79 VGPRs).  Same arithmetic.
 template <int FROM_R, int PRE>
 __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ sblocks,
                                                     const PairGeo* __restrict__ geo,
@@ -1010,9 +1009,7 @@ __global__ __launch_bounds__(kWG) void k_pair_sums_from_R(const PBlock* __restri
 template <int FROM_R>
 static void launch_solve(const LaunchArgs& a, const PairCtl* ctl, PairCtl* ctl_next,
                          const double* rowsum, hipStream_t st) {
-  // by launch size: at most four blocks per CU (256 CUs), the solve is
-  // latency-bound and the early loads pay
-  if (a.solve_pre > 0 || (a.solve_pre < 0 && a.nsblocks <= 1024))
+  if (a.solve_pre != 0)
     hipLaunchKernelGGL((k_pair_solve<FROM_R, 1>), dim3(a.nsblocks), dim3(kWG), 0, st, a.sblocks,
                        a.geo, ctl, ctl_next, rowsum, a.arr, a.vec, a.ab);
   else

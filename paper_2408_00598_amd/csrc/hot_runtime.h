@@ -33,7 +33,7 @@ struct Tuning {
   int fuse;             // default for one slab kernel for every pass
   int row_group;        // > 0: slabs per solve wave and slots per reduce block (else by launch size)
   int reduce_group;     // > 0: slots per reduce block (overrides row_group for the reduce)
-  int solve_pre;        // solve loads before the decision: -1 by launch size, 0 never, 1 always
+  int solve_pre;        // 1: the solve issues its decision-free loads before the decision, 0: after
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
@@ -82,7 +82,7 @@ struct LaunchArgs {
   int coord = 0;      // some pair has non-uniform bins: slab passes read positions
   int su = 0;         // some pair re-balances sigma at restarts
   int fuse = 0;       // one slab kernel for plain, check and restart passes
-  int solve_pre = -1; // solve loads before the decision: -1 by launch size, 0 never, 1 always
+  int solve_pre = 1;  // the solve issues its decision-free loads before the decision
   void* sbx = nullptr;      // x_bar of the last restart (sigma re-balancing), else null
   double* abY = nullptr;    // alpha / beta of the last restart (sigma re-balancing)
   unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes
