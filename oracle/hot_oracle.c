@@ -261,6 +261,10 @@ void or_kkt_xy(int32_t m, int32_t n, const double *cu, const double *cv,
     msum += v * v;
   }
   const double rp2 = dot(M3, r, r);
+  /* negative part of x for the feasibility error of Sec. 4.1 */
+  double nsum = 0.0;
+  for (int64_t e = 0; e < N; ++e)
+    if (x[e] < 0.0) nsum += x[e] * x[e];
   res->kkt_abs = sqrt(rp2 + msum + dsum);
   res->res_dual = sqrt(dsum) / (1.0 + nrm2(N, c));
   res->res_comp = sqrt(csum) / (1.0 + nrm2(N, x) + nrm2(N, z));
@@ -269,6 +273,10 @@ void or_kkt_xy(int32_t m, int32_t n, const double *cu, const double *cv,
   if (res->res_comp > k) k = res->res_comp;
   if (res->res_primal > k) k = res->res_primal;
   res->kkt = k;
+  {
+    const double fneg = sqrt(nsum) / (1.0 + nrm2(N, x));
+    res->feaserr = fneg > res->res_primal ? fneg : res->res_primal;
+  }
   res->primal_obj = dot(N, c, x);
   res->dual_obj = dot(M3, b, y);
   free(c); free(b); free(v); free(r);
@@ -315,9 +323,21 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   const int32_t T = p->check_every > 0 ? p->check_every : 1;
   const int32_t fixed = p->fixed_iters > 0 ? p->fixed_iters : 0;
 
-  int32_t k = 0, it = 0, restarts = 0, converged = 0;
+  int32_t k = 0, it = 0, restarts = 0, converged = 0, ntrace = 0;
   double r_start = 0.0, r_prev = 0.0, r_last = 0.0;
   memset(res, 0, sizeof(*res));
+  /* one record per check: (it, k, r, restarted) */
+#define OR_TRACE(flag)                                   \
+  do {                                                   \
+    if (p->trace && ntrace < p->trace_cap) {             \
+      double *t_ = p->trace + 4 * (int64_t)ntrace;       \
+      t_[0] = (double)it;                                \
+      t_[1] = (double)k;                                 \
+      t_[2] = r_last;                                    \
+      t_[3] = (flag);                                    \
+      ++ntrace;                                          \
+    }                                                    \
+  } while (0)
   for (;;) {
     /* Step 1: A A^T y_bar = b/sigma - A(x/sigma + z - c) */
     OR_PARALLEL_FOR
@@ -348,6 +368,11 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
         }
         r_last = 2.0 * sqrt(acc);
         const double crit = p->abs_kkt ? res->kkt_abs : res->kkt;
+        const int32_t restart_now =
+            p->restart && !(p->admm_rho > 0) && k > 0 &&
+            (r_last <= 0.2 * r_start || (r_last <= 0.8 * r_start && r_last > r_prev));
+        const int32_t stop = (p->tol > 0 && crit <= p->tol) || last;
+        OR_TRACE((!stop && restart_now) ? 1.0 : 0.0);
         if (p->tol > 0 && crit <= p->tol) {
           converged = 1;
           break;
@@ -357,8 +382,7 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
           if (k == 0) {
             r_start = r_last;
             r_prev = r_last;
-          } else if (r_last <= 0.2 * r_start ||
-                     (r_last <= 0.8 * r_start && r_last > r_prev)) {
+          } else if (restart_now) {
             if (p->sigma_update) {
               /* primal / dual displacement over the epoch that ends here:
                * dx = ||x_bar - X||, dy = ||A^T (y_bar - Y)||; the ratio puts
@@ -422,6 +446,8 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   res->iters = it;
   res->restarts = restarts;
   res->converged = converged;
+  res->ntrace = ntrace;
+#undef OR_TRACE
   free(c); free(b); free(x); free(z); free(y); free(x0); free(z0); free(y0);
   free(tmp); free(aty); free(R); free(Xr); free(Yr);
   return converged;

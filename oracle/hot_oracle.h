@@ -39,6 +39,10 @@ typedef struct {
   const double *coord_col; /* n grid-line positions v_j, or NULL for v_j = j */
   int32_t sigma_update; /* 1: at every restart, sigma <- ||x_bar - X|| / ||A^T (y_bar - Y)||
                            with (X, Y) the w_bar of the previous restart (w^0 = 0 at first) */
+  double *trace;       /* nullable: 4 doubles per check (iteration count it, epoch
+                          counter k, fixed-point residual r, 1 if the check
+                          restarts the epoch else 0), at most trace_cap checks */
+  int32_t trace_cap;
 } or_params;
 
 typedef struct {
@@ -51,9 +55,12 @@ typedef struct {
   double sigma;
   double fp_res;       /* ||s - shat|| with s = x/sigma + z: fixed-point residual */
   double kkt_abs;      /* ||R(w_bar)||: the residual map of the complexity proposition */
+  double feaserr;      /* max(||min(xbar, 0)|| / (1 + ||xbar||), res_primal): the
+                          relative primal feasibility error of the experiments (Sec. 4.1) */
   int32_t iters;       /* number of updates performed */
   int32_t restarts;
   int32_t converged;
+  int32_t ntrace;      /* checks recorded in or_params.trace */
 } or_result;
 
 void or_dims(int32_t m, int32_t n, int64_t *N, int64_t *M3);

@@ -21,7 +21,8 @@ class Params(C.Structure):
                 ("check_every", C.c_int32), ("sigma", C.c_double),
                 ("restart", C.c_int32), ("fixed_iters", C.c_int32),
                 ("admm_rho", C.c_double), ("abs_kkt", C.c_int32),
-                ("coord_row", D), ("coord_col", D), ("sigma_update", C.c_int32)]
+                ("coord_row", D), ("coord_col", D), ("sigma_update", C.c_int32),
+                ("trace", D), ("trace_cap", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -29,8 +30,9 @@ class Result(C.Structure):
                 ("kkt", C.c_double), ("res_dual", C.c_double),
                 ("res_comp", C.c_double), ("res_primal", C.c_double),
                 ("sigma", C.c_double), ("fp_res", C.c_double), ("kkt_abs", C.c_double),
+                ("feaserr", C.c_double),
                 ("iters", C.c_int32), ("restarts", C.c_int32),
-                ("converged", C.c_int32)]
+                ("converged", C.c_int32), ("ntrace", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -154,21 +156,28 @@ def kkt(mu1, mu2, x, y, z, coord_row=None, coord_col=None):
 
 def hot(mu1, mu2, tol=1e-6, max_iter=100000, check_every=10, sigma=0.0,
         restart=True, fixed_iters=0, admm_rho=0.0, abs_kkt=False, coord_row=None,
-        coord_col=None, sigma_update=False, threads=False):
+        coord_col=None, sigma_update=False, threads=False, trace=0):
     """Run Algorithm 2; returns (xbar, ybar, zbar, s_state, result dict).
-    threads: the OpenMP build (multi-core timing; identical results)."""
+    threads: the OpenMP build (multi-core timing; identical results).
+    trace > 0: the result dict also holds "trace", one row (it, k, r,
+    restarted) per check, at most `trace` rows."""
     mu1, mu2 = _f64(mu1), _f64(mu2)
     m, n = mu1.shape
     N, M3 = dims(m, n)
     xb, zb, s = np.empty(N), np.empty(N), np.empty(N)
     yb = np.empty(M3)
     u, v = _coords(m, n, coord_row, coord_col)
+    tr = np.zeros((max(int(trace), 1), 4))
     p = Params(tol, max_iter, check_every, sigma, 1 if restart else 0, fixed_iters, admm_rho,
-               1 if abs_kkt else 0, _dn(u), _dn(v), 1 if sigma_update else 0)
+               1 if abs_kkt else 0, _dn(u), _dn(v), 1 if sigma_update else 0,
+               _d(tr) if trace > 0 else None, int(trace))
     r = Result()
     lib(threads).or_hot(m, n, _d(mu1), _d(mu2), C.byref(p), _d(xb), _d(yb), _d(zb), _d(s),
                         C.byref(r))
-    return xb, yb, zb, s, r.as_dict()
+    out = r.as_dict()
+    if trace > 0:
+        out["trace"] = tr[:r.ntrace].copy()
+    return xb, yb, zb, s, out
 
 
 def recover(m, n, x, cap=None):
