@@ -113,6 +113,9 @@ typedef struct {
   int32_t restarts;
   int32_t status;     /* hot_status of this problem */
   int32_t reserved;
+  double feaserr;     /* max(||min(x_bar, 0)|| / (1 + ||x_bar||), res_primal): the
+                         relative primal feasibility error of the experiments
+                         (Sec. 4.1, the metric feaserr) */
 } hot_result;
 
 typedef struct hot_ctx hot_ctx;
@@ -135,7 +138,9 @@ typedef struct hot_server hot_server;
  * issues its decision-free loads before / after the decision; results
  * unchanged).
  * HOT_NO_GRAPH=1 launches every iteration directly instead of through
- * captured graphs. */
+ * captured graphs.  HOT_TEST_NAN_AFTER=q (failure-path tests only) makes
+ * hot_solve write a NaN into the flow state between graph launch q and q+1,
+ * so that the solve must end with HOT_E_NUMERIC. */
 hot_status hot_ctx_create(int device, hot_ctx **out);
 void hot_ctx_destroy(hot_ctx *ctx);
 
@@ -205,6 +210,18 @@ hot_status hot_solution_export(hot_ctx *ctx, const hot_solution *sol,
                                double *zbar, double *s);
 void hot_solution_free(hot_solution *sol);
 
+/* The Halpern anchor of the final epoch (Algorithm 2, Step 4: the point w^0
+ * the epoch's updates are pulled toward, here the state s^0 = x^0/sigma + z^0
+ * the epoch restarted from, or 0 before the first restart) in the paper's
+ * ordering, into a caller-owned DEVICE buffer of N doubles (nullable), and
+ * (host, nullable, 4 doubles) the control values the solve ended with:
+ * info[0] the epoch counter k of the last update, info[1] the Halpern weight
+ * 1/(k+2) of the next update (1 - rho/2 for the ADMM baseline), info[2]
+ * sigma, info[3] 0 if the anchor is zero, 1 if it is the state itself (ADMM
+ * baseline, first update after a restart), 2 if it is a buffer of its own. */
+hot_status hot_solution_anchor(hot_ctx *ctx, const hot_solution *sol,
+                               hot_stream_t stream, double *s0, double *info);
+
 /* Algorithm 1 on the clipped flows max(x_bar, 0) of `sol`, followed by the
  * marginal repair (rows above mu1 scaled down, then columns above mu2, then
  * the remaining deficits coupled north-west-corner in bin order).  Writes
@@ -247,7 +264,10 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
 /* Continuous-batching service.  A worker thread admits queued problems
  * (FIFO) whenever fewer than max_slots are resident and the sum of their
  * device footprints (hot_footprint_bytes) stays within hbm_budget_bytes
- * (0: 80% of the free device memory at creation).  Each resident problem is
+ * (0: 80% of the free device memory at creation; footprints are computed
+ * with the context's launch-shape tuning, and workspaces kept for reuse after
+ * a problem finishes count against the budget until they are freed to admit
+ * another problem).  Each resident problem is
  * iterated on its own stream by its captured graph, so problems admitted at
  * different times run concurrently; iterates stay on the device until the
  * problem stops.  A problem's result equals its hot_solve result.
@@ -261,6 +281,10 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
  *   timeout).
  * stats: out[8] = completed, submitted, queued, resident, bytes resident,
  *   most resident at once, p50 latency, p99 latency (seconds).
+ * cancel: every problem submitted so far ends with HOT_E_CANCELLED (queued
+ *   ones at once, resident ones after their current quantum, with their last
+ *   iterate's values in the result) unless it has already finished; results
+ *   are polled as usual and the server keeps accepting new problems.
  * destroy: drops queued problems, stops resident ones after their current
  *   quantum (their results, not polled, are discarded), frees all. */
 typedef struct {
@@ -277,6 +301,7 @@ int32_t hot_server_poll(hot_server *srv, hot_result *results, uint64_t *tags,
                         double *latency_s, int32_t max);
 hot_status hot_server_drain(hot_server *srv, double timeout_s);
 hot_status hot_server_stats(hot_server *srv, double *out);
+hot_status hot_server_cancel(hot_server *srv);
 void hot_server_destroy(hot_server *srv);
 
 #ifdef __cplusplus

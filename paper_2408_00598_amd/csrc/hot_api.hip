@@ -33,12 +33,13 @@ void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st);
 void launch_setup_mu(const double* mu1, const double* mu2, int m, int n, double* mu1T,
                      double* mu2c, hipStream_t st);
 void launch_export(const LaunchArgs& a, int par, int pair, int64_t N, double* xbar,
-                   double* zbar, double* sout, hipStream_t st);
+                   double* zbar, double* sout, hipStream_t st, double* s0out = nullptr);
 void launch_export_y(const LaunchArgs& a, int pair, int64_t M3, double* y, hipStream_t st);
 void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
                       hipStream_t st);
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
                              double* out, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
 
 static int next_pow2(int v) {
   int p = 1;
@@ -306,6 +307,9 @@ void Workspace::drop_retired() {
 
 void Workspace::release() {
   drop_retired();
+  if (stage_ev) (void)hipEventDestroy(stage_ev);
+  stage_ev = nullptr;
+  stage_pending = false;
   if (stage_h) (void)hipHostFree(stage_h);
   stage_h = nullptr;
   if (quantum_event) (void)hipEventDestroy(quantum_event);
@@ -322,17 +326,21 @@ void Workspace::release() {
   stream = nullptr;
 }
 
+// One device buffer.
+hot_status Workspace::device_buffer(hot_ctx* ctx, void** p, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (ctx) ctx->err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+    return HOT_E_NOMEM;
+  }
+  allocs.push_back(*p);
+  return HOT_OK;
+}
+
 hot_status Workspace::alloc_all(hot_ctx* ctx) {
-  auto A = [&](void** p, size_t bytes) -> hot_status {
-    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      if (ctx) ctx->err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
-      return HOT_E_NOMEM;
-    }
-    allocs.push_back(*p);
-    return HOT_OK;
-  };
+  auto A = [&](void** p, size_t bytes) -> hot_status { return device_buffer(ctx, p, bytes); };
   hot_status st;
   const size_t es = lay.elem_size;
   for (int b = 0; b < 3; ++b)
@@ -558,22 +566,15 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
         !(probs[p].flags & (HOT_FLAG_FIXED_ITERS | HOT_FLAG_ADMM)))
       su = 1;
   if (su && !sbx) {
-    const size_t xb = std::max<size_t>((size_t)lay.state_elems * lay.elem_size, 256);
-    const size_t yb = std::max<size_t>((size_t)lay.tab_off * 8, 256);
+    const size_t xb = (size_t)lay.state_elems * lay.elem_size;
+    const size_t yb = (size_t)lay.tab_off * 8;
     void* xbuf = nullptr;
     void* ybuf = nullptr;
-    const bool okx = hipMalloc(&xbuf, xb) == hipSuccess;
-    const bool oky = okx && hipMalloc(&ybuf, yb) == hipSuccess;
-    if (!oky) {
-      (void)hipGetLastError();
-      if (okx) (void)hipFree(xbuf);
-      ctx->err = "hipMalloc failed (sigma re-balancing buffers)";
-      return HOT_E_NOMEM;
-    }
+    hot_status s1 = device_buffer(ctx, &xbuf, xb);
+    if (s1 == HOT_OK) s1 = device_buffer(ctx, &ybuf, yb);
+    if (s1 != HOT_OK) return s1;
     sbx = xbuf;
     abY = (double*)ybuf;
-    allocs.push_back(sbx);
-    allocs.push_back(abY);
   }
   const int variant = coord | (su << 1);
   if (graph_exec && graph_variant != variant) {  // captured with other slab kernels
@@ -631,23 +632,25 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     launch_setup_mu(probs[p].mu1, probs[p].mu2, g.m, g.n, arr + arr_mu1T(g), arr + arr_mu2(g),
                     st);
   }
-  HIPCK(hipGetLastError());
-  HIPCK(hipMemsetAsync(sb[0], 0, (size_t)lay.state_elems * lay.elem_size, st));
-  if (ctx->tune.sep_anchor)
-    HIPCK(hipMemsetAsync(sb[2], 0, (size_t)lay.state_elems * lay.elem_size, st));
+  // zero fills by a kernel (no memset nodes, should a caller capture this)
+  launch_zero(sb[0], (size_t)lay.state_elems * lay.elem_size, st);
+  if (ctx->tune.sep_anchor) launch_zero(sb[2], (size_t)lay.state_elems * lay.elem_size, st);
   for (int q = 0; q < 2; ++q) {
-    HIPCK(hipMemsetAsync(rowsum[q], 0, lay.rs_len * 8, st));
-    HIPCK(hipMemsetAsync(colpart[q], 0, lay.cp_len * 8, st));
+    launch_zero(rowsum[q], lay.rs_len * 8, st);
+    launch_zero(colpart[q], lay.cp_len * 8, st);
   }
-  HIPCK(hipMemsetAsync(ab, 0, lay.ab_len * 8, st));
+  launch_zero(ab, lay.ab_len * 8, st);
   if (args.su) {  // X = 0, Y = 0 before the first restart (the initial point)
-    HIPCK(hipMemsetAsync(sbx, 0, (size_t)lay.state_elems * lay.elem_size, st));
-    HIPCK(hipMemsetAsync(abY, 0, (size_t)lay.tab_off * 8, st));
+    launch_zero(sbx, (size_t)lay.state_elems * lay.elem_size, st);
+    launch_zero(abY, (size_t)lay.tab_off * 8, st);
   }
   HIPCK(hipMemcpyAsync(ab + lay.tab_off, tab_host.data(), (size_t)lay.tab_len * 8,
                        hipMemcpyHostToDevice, st));
-  HIPCK(hipMemsetAsync(kitem, 0, lay.items.size() * kKI * 8, st));
-  HIPCK(hipMemsetAsync(bytes_ctr, 0, 8, st));
+  launch_zero(kitem, lay.items.size() * kKI * 8, st);
+  launch_zero(bytes_ctr, 8, st);
+  HIPCK(hipGetLastError());
+  // the host buffers above are pageable and the copies may still read them
+  HIPCK(hipStreamSynchronize(st));
   return HOT_OK;
 }
 
@@ -697,6 +700,8 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
   while (e == hipSuccess) {
     // keep one graph in flight while the previous one's status is read
     if (launched < max_graphs) {
+      if (launched == nan_after) e = poison_state(st);
+      if (e != hipSuccess) break;
       e = launch_one(cur ^ 1);
       if (e != hipSuccess) break;
       ++launched;
@@ -732,6 +737,22 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
     }
   }
   return result;
+}
+
+// Failure-path test hook: a NaN into the first flow element of every state
+// buffer (whichever the next pass reads), ordered on the stream between two
+// graphs.  Only contexts created with HOT_TEST_NAN_AFTER set ever call it.
+hipError_t Workspace::poison_state(hipStream_t st) {
+  static const double nan64 = std::nan("");
+  static const float nan32 = std::nanf("");
+  const void* src = lay.fp32 ? (const void*)&nan32 : (const void*)&nan64;
+  const int64_t off = std::min(lay.geo[0].f[0].soff, lay.geo[0].f[1].soff);
+  for (int b = 0; b < 3; ++b) {
+    hipError_t e = hipMemcpyAsync((char*)sb[b] + off * lay.elem_size, src, lay.elem_size,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Profiling run: direct launches, a hipEvent pair around every slab pass on
@@ -805,6 +826,13 @@ hot_status Workspace::compact(hot_ctx* ctx, const PairCtl* hc) {
       ++active;
     }
   if (active == 0 || 2 * active > launch_pairs) return HOT_OK;
+  // the previous compaction's uploads read stage_h asynchronously, queued
+  // behind graphs that may still run: wait for them before rewriting it
+  if (stage_pending) {
+    HIPCK(hipEventSynchronize(stage_ev));
+    stage_pending = false;
+  }
+  if (!stage_ev) HIPCK(hipEventCreateWithFlags(&stage_ev, hipEventDisableTiming));
   SlabItem* it = (SlabItem*)stage_h;
   SmallItem* si = (SmallItem*)((char*)stage_h + std::max<size_t>(lay.items.size(), 1) * sizeof(SlabItem));
   PBlock* bl = (PBlock*)((char*)si + std::max<size_t>(lay.sitems.size(), 1) * sizeof(SmallItem));
@@ -828,6 +856,8 @@ hot_status Workspace::compact(hot_ctx* ctx, const PairCtl* hc) {
                          stream));
   HIPCK(hipMemcpyAsync(blocks_c, bl, (size_t)nbl * sizeof(PBlock), hipMemcpyHostToDevice, stream));
   HIPCK(hipMemcpyAsync(sblocks_c, sb, (size_t)nsb * sizeof(PBlock), hipMemcpyHostToDevice, stream));
+  HIPCK(hipEventRecord(stage_ev, stream));
+  stage_pending = true;
   if (graph_exec) retired.push_back({graph, graph_exec});
   graph = nullptr;
   graph_exec = nullptr;
@@ -900,6 +930,7 @@ void Workspace::fill_result(int p, hot_result* r, double seconds) const {
   r->iters = c.it;
   r->restarts = c.restarts;
   r->status = (int32_t)status_of(c.status);
+  r->feaserr = c.feaserr;
 }
 
 }  // namespace hot
@@ -965,6 +996,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.pingpong = std::atoi(e) != 0;
   e = std::getenv("HOT_UNROLL");
   if (e) c->tune.unroll = std::atoi(e) >= 2 ? 2 : 1;
+  e = std::getenv("HOT_TEST_NAN_AFTER");
+  if (e) c->nan_after = std::max(1, std::atoi(e));
   *out = c;
   return HOT_OK;
 }
@@ -1035,6 +1068,7 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
   }
   ws->device = ctx->device;
   ws->profile = ctx->profiling;
+  ws->nan_after = ctx->nan_after;
   hot_status s = ws->alloc_all(ctx);
   {
     int64_t total = 0;
@@ -1252,6 +1286,27 @@ hot_status hot_solution_export(hot_ctx* ctx, const hot_solution* sol, hot_stream
   if (ybar) launch_export_y(sol->ws->args, sol->pair, 3 * M - 1, ybar, st);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(st));
+  return HOT_OK;
+}
+
+hot_status hot_solution_anchor(hot_ctx* ctx, const hot_solution* sol, hot_stream_t stream,
+                               double* s0, double* info) {
+  if (!ctx || !sol) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const int64_t m = sol->m, n = sol->n;
+  const int64_t N = m * m * n + m * n * n;
+  hipStream_t st = (hipStream_t)stream;
+  if (s0) launch_export(sol->ws->args, 0, sol->pair, N, nullptr, nullptr, nullptr, st, s0);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));
+  if (info) {
+    // the control block the solve ended with (the last copy is ctl[0])
+    const PairCtl& c = sol->ws->host_ctl[sol->pair];
+    info[0] = (double)c.k;
+    info[1] = c.lam;
+    info[2] = c.sigma;
+    info[3] = c.anc < 0 ? 0.0 : (c.anc == c.src ? 1.0 : 2.0);
+  }
   return HOT_OK;
 }
 

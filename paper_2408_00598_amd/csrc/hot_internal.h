@@ -47,10 +47,14 @@ enum PairStatus : int32_t {
 };
 
 // per-item partial indices (slab pass, check mode)
-enum KItem : int { KI_DUAL = 0, KI_COMP, KI_XX, KI_ZZ, KI_CX, KI_FP, KI_DX };
+// (KI_NEG: ||min(x_bar, 0)||^2, the first term of the feasibility error of
+// the experiments)
+enum KItem : int { KI_DUAL = 0, KI_COMP, KI_XX, KI_ZZ, KI_CX, KI_FP, KI_DX, KI_NEG };
 // per-block partial indices (pair reduce, check mode)
-enum KPart : int { KP_DUAL = 0, KP_COMP, KP_XX, KP_ZZ, KP_CX, KP_FP, KP_DX, KP_PRIM, KP_BY, KP_DY };
-constexpr int kNKP = 10;  // partials per reduce block in use (of kKP slots)
+enum KPart : int {
+  KP_DUAL = 0, KP_COMP, KP_XX, KP_ZZ, KP_CX, KP_FP, KP_DX, KP_PRIM, KP_BY, KP_DY, KP_NEG
+};
+constexpr int kNKP = 11;  // partials per reduce block in use (of kKP slots)
 
 struct FamGeo {
   int32_t L;       // slab side
@@ -156,6 +160,7 @@ struct PairCtl {
   double r_start, r_prev;
   double kkt, res_p, res_d, res_c, pobj, dobj, fp_res;
   double kkt_abs, relax;  // ||R(w_bar)||; rho of the ADMM baseline (0: Halpern)
+  double feaserr;         // max(||min(x_bar, 0)|| / (1 + ||x_bar||), res_p)
   double sig_old;         // restart pass with sigma re-balancing: sigma of x_bar
   int32_t k, it, restarts, status;
   int32_t mode, src, dst, anc;

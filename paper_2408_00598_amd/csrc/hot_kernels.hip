@@ -262,12 +262,14 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     if (mode != MODE_CHECK) continue;
 
     // ---- check pass: KKT partials of w_bar^k -------------------------------
-    double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     {
       const int i0 = G.item0 + slot * G.ipb;
       const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
-      for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
+      for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG) {
         for (int q = 0; q <= KI_DX; ++q) part[q] += kitem[(int64_t)it * kKI + q];
+        part[KP_NEG] += kitem[(int64_t)it * kKI + KI_NEG];
+      }
     }
     if (su && has_slab) {
       // ||A^T (y_bar - Y)||^2 over this slab: A^T y is alpha_p + beta_q on it,
@@ -393,6 +395,7 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
       nx.res_p = sqrt(acc[KP_PRIM]) / (1.0 + G.norm_b);
       nx.kkt = fmax(nx.res_d, fmax(nx.res_c, nx.res_p));
       nx.kkt_abs = sqrt(acc[KP_PRIM] + acc[KP_COMP] + acc[KP_DUAL]);
+      nx.feaserr = fmax(sqrt(acc[KP_NEG]) / (1.0 + nx2), nx.res_p);
       const double crit = (c.flags & 8) ? nx.kkt_abs : nx.kkt;
       nx.pobj = acc[KP_CX];
       nx.dobj = acc[KP_BY];
@@ -837,6 +840,16 @@ __global__ __launch_bounds__(kWG) void k_hist_stats_multi(const double* const* _
   }
 }
 
+// Zero fill: 16-byte stores over the aligned body, 4-byte stores for a tail
+// (every buffer is 256-byte aligned and a multiple of 4 bytes long).
+__global__ void k_zero(uint4* __restrict__ p, int64_t n16, uint32_t* __restrict__ tail,
+                       int64_t ntail) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t q = t0; q < n16; q += stride) p[q] = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t q = t0; q < ntail; q += stride) tail[q] = 0u;
+}
+
 // mu1T[j][i] = mu1[i][j], mu2[k][l] copied.
 __global__ void k_setup_mu(const double* __restrict__ mu1, const double* __restrict__ mu2,
                            int m, int n, double* __restrict__ mu1T, double* __restrict__ mu2c) {
@@ -855,12 +868,14 @@ __global__ void k_export(const PairGeo* __restrict__ geo, const PairCtl* __restr
                          const T* __restrict__ sb0, const T* __restrict__ sb1,
                          const T* __restrict__ sb2, const double* __restrict__ ab,
                          double* __restrict__ xbar, double* __restrict__ zbar,
-                         double* __restrict__ sout) {
+                         double* __restrict__ sout, double* __restrict__ s0out) {
   const PairGeo G = geo[pair];
   const PairCtl c = ctl[pair];
   const int m = G.m, n = G.n;
   const int64_t N1 = (int64_t)m * m * n, N = N1 + (int64_t)m * n * n;
   const T* s = pick<const T>(sb0, sb1, sb2, c.src);
+  // the Halpern anchor of the epoch: zero before the first restart
+  const T* s0 = c.anc >= 0 ? pick<const T>(sb0, sb1, sb2, c.anc) : nullptr;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N;
        e += (int64_t)gridDim.x * blockDim.x) {
     int fam, slab, p, q, L;
@@ -877,7 +892,9 @@ __global__ void k_export(const PairGeo* __restrict__ geo, const PairCtl* __restr
       fam = 1; slab = k; p = j; q = l; L = n;
     }
     const FamGeo F = G.f[fam];
-    const double sv = (double)s[F.soff + ((int64_t)slab * L + p) * F.P + q];
+    const int64_t at = F.soff + ((int64_t)slab * L + p) * F.P + q;
+    const double sv = (double)s[at];
+    if (s0out) s0out[e] = s0 ? (double)s0[at] : 0.0;
     const double* al = ab + F.aboff + (int64_t)slab * 2 * L;
     const double* X = fam_x(ab, F);
     const double d = X[p] - X[q];
@@ -1040,6 +1057,15 @@ void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int
   hipLaunchKernelGGL(k_hist_stats_multi, dim3(count), dim3(kWG), 0, st, ptrs, lens, out);
 }
 
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (!p || bytes < 4) return;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int64_t ntail = (int64_t)((bytes - 16 * (size_t)n16) / 4);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n16 + kWG - 1) / kWG, 8192));
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(kWG), 0, st, (uint4*)p, n16,
+                     (uint32_t*)((char*)p + 16 * n16), ntail);
+}
+
 void launch_setup_mu(const double* mu1, const double* mu2, int m, int n, double* mu1T,
                      double* mu2c, hipStream_t st) {
   const int64_t M = (int64_t)m * n;
@@ -1048,16 +1074,16 @@ void launch_setup_mu(const double* mu1, const double* mu2, int m, int n, double*
 }
 
 void launch_export(const LaunchArgs& a, int par, int pair, int64_t N, double* xbar,
-                   double* zbar, double* sout, hipStream_t st) {
+                   double* zbar, double* sout, hipStream_t st, double* s0out) {
   const int grid = (int)std::min<int64_t>((N + kWG - 1) / kWG, 65536);
   if (a.fp32)
     hipLaunchKernelGGL(k_export<float>, dim3(grid), dim3(kWG), 0, st, a.geo, a.ctl[par], pair,
                        (const float*)a.sb[0], (const float*)a.sb[1], (const float*)a.sb[2], a.ab,
-                       xbar, zbar, sout);
+                       xbar, zbar, sout, s0out);
   else
     hipLaunchKernelGGL(k_export<double>, dim3(grid), dim3(kWG), 0, st, a.geo, a.ctl[par], pair,
                        (const double*)a.sb[0], (const double*)a.sb[1], (const double*)a.sb[2],
-                       a.ab, xbar, zbar, sout);
+                       a.ab, xbar, zbar, sout, s0out);
 }
 
 void launch_export_y(const LaunchArgs& a, int pair, int64_t M3, double* y, hipStream_t st) {

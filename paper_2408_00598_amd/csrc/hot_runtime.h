@@ -143,6 +143,8 @@ struct Workspace {
   PBlock* blocks_c = nullptr;
   PBlock* sblocks_c = nullptr;
   void* stage_h = nullptr;
+  hipEvent_t stage_ev = nullptr;  // recorded after the last upload from stage_h
+  bool stage_pending = false;
   int launch_pairs = 0;
   std::vector<std::pair<hipGraph_t, hipGraphExec_t>> retired;
   hot_status compact(hot_ctx* ctx, const PairCtl* hc);
@@ -157,8 +159,13 @@ struct Workspace {
   int64_t prof_launches = 0;
   int64_t iterations_launched = 0;
 
+  // test hook (HOT_TEST_NAN_AFTER): after this many graphs, write a NaN into
+  // the first flow element of every state buffer; < 0 off
+  int64_t nan_after = -1;
+
   ~Workspace();
   void release();
+  hot_status device_buffer(hot_ctx* ctx, void** p, size_t bytes);
   hot_status alloc_all(hot_ctx* ctx);
   hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
   hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
@@ -166,6 +173,7 @@ struct Workspace {
   // launch one graph (kGraphIters iterations) + status copy + event.
   hot_status ensure_graph(hot_ctx* ctx, hipStream_t st);
   hipError_t launch_quantum(hipStream_t st);
+  hipError_t poison_state(hipStream_t st);
   hipEvent_t quantum_event = nullptr;
   hot_status run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
   void fill_result(int p, hot_result* r, double seconds) const;
@@ -194,6 +202,7 @@ struct hot_ctx {
   std::mutex mu;
   std::string err;
   hot::Tuning tune = hot::default_tuning();
+  int64_t nan_after = -1;  // HOT_TEST_NAN_AFTER (failure-path tests only)
   // measurement counters (hot_ctx_profile_read)
   bool profiling = false;
   double prof_seconds = 0, prof_launches = 0, prof_bytes = 0, iters_launched = 0;

@@ -42,6 +42,7 @@ struct Request {
   hot_problem prob;
   uint64_t tag;
   double t_submit;
+  uint64_t gen;  // cancellation generation at submission
 };
 
 struct Slot {
@@ -71,10 +72,12 @@ struct hot_server {
   std::deque<Request> queue;
   std::vector<Done> done;
   std::vector<double> latencies;
-  std::multimap<ShapeKey, std::shared_ptr<Workspace>> pool;
+  std::multimap<ShapeKey, std::pair<std::shared_ptr<Workspace>, size_t>> pool;
   size_t pool_count = 0;
+  size_t pool_bytes = 0;  // device bytes held by pooled workspaces
   std::thread th;
   std::atomic<bool> stop{false};
+  std::atomic<uint64_t> cancel_gen{0};  // requests of earlier generations are cancelled
   // counters (guarded by mu)
   int64_t submitted = 0, completed = 0;
   int active = 0, max_active = 0;
@@ -100,29 +103,43 @@ static void server_loop(hot_server* S) {
     for (;;) {
       Request req;
       size_t bytes = 0;
+      std::shared_ptr<Workspace> ws;
+      std::vector<std::shared_ptr<Workspace>> evicted;  // freed outside the lock
       {
         std::unique_lock<std::mutex> lk(S->mu);
         if (S->queue.empty() || (int)slots.size() >= S->max_slots) break;
-        bytes = footprint_of(S->queue.front().prob, tmp.tune);
-        if (!slots.empty() && S->in_use + bytes > S->budget) break;  // wait for memory
+        const Request& head = S->queue.front();
+        bytes = footprint_of(head.prob, tmp.tune);
+        // a pooled workspace of this shape is reused; pooled memory counts
+        // against the budget, so others are freed when it would not fit
+        const ShapeKey key{head.prob.m, head.prob.n, head.prob.prec};
+        auto hit = S->pool.find(key);
+        const size_t reuse = hit != S->pool.end() ? hit->second.second : 0;
+        while (S->in_use + S->pool_bytes - reuse + bytes > S->budget) {
+          auto victim = S->pool.begin();
+          while (victim != S->pool.end() && victim == hit) ++victim;
+          if (victim == S->pool.end()) break;
+          S->pool_bytes -= victim->second.second;
+          --S->pool_count;
+          evicted.push_back(victim->second.first);
+          S->pool.erase(victim);
+        }
+        if (!slots.empty() && S->in_use + S->pool_bytes - reuse + bytes > S->budget)
+          break;  // wait for memory
+        if (hit != S->pool.end()) {
+          ws = hit->second.first;
+          S->pool_bytes -= hit->second.second;
+          --S->pool_count;
+          S->pool.erase(hit);
+        }
         req = S->queue.front();
         S->queue.pop_front();
         S->in_use += bytes;
         S->active = (int)slots.size() + 1;
         S->max_active = std::max(S->max_active, S->active);
       }
+      evicted.clear();
       progressed = true;
-      const ShapeKey key{req.prob.m, req.prob.n, req.prob.prec};
-      std::shared_ptr<Workspace> ws;
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        auto it = S->pool.find(key);
-        if (it != S->pool.end()) {
-          ws = it->second;
-          S->pool.erase(it);
-          --S->pool_count;
-        }
-      }
       hot_status st = HOT_OK;
       if (!ws) st = make_workspace(&tmp, &req.prob, 1, ws);
       if (st == HOT_OK) st = ws->setup(&tmp, &req.prob, 1, ws->stream);
@@ -161,7 +178,7 @@ static void server_loop(hot_server* S) {
       }
       progressed = true;
       const bool running = (e == hipSuccess) && sl.ws->host_ctl[0].status == ST_RUNNING;
-      const bool cancel = S->stop.load();
+      const bool cancel = S->stop.load() || sl.req.gen < S->cancel_gen.load();
       if (running && !cancel && sl.quanta < sl.max_quanta) {
         if (sl.ws->launch_quantum(sl.ws->stream) == hipSuccess) {
           ++sl.quanta;
@@ -186,8 +203,10 @@ static void server_loop(hot_server* S) {
         ++S->completed;
         S->in_use -= sl.bytes;
         if (S->pool_count < (size_t)(2 * S->max_slots) && e == hipSuccess) {
-          S->pool.emplace(ShapeKey{sl.req.prob.m, sl.req.prob.n, sl.req.prob.prec}, sl.ws);
+          S->pool.emplace(ShapeKey{sl.req.prob.m, sl.req.prob.n, sl.req.prob.prec},
+                          std::make_pair(sl.ws, sl.bytes));
           ++S->pool_count;
+          S->pool_bytes += sl.bytes;
         }
         S->active = (int)slots.size() - 1;
         S->cv.notify_all();
@@ -248,6 +267,7 @@ hot_status hot_server_submit(hot_server* S, const hot_problem* prob, uint64_t ta
   r.t_submit = now_s();
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    r.gen = S->cancel_gen.load();
     S->queue.push_back(r);
     ++S->submitted;
   }
@@ -299,6 +319,27 @@ hot_status hot_server_stats(hot_server* S, double* out) {
   out[5] = (double)S->max_active;
   out[6] = pct(0.50);
   out[7] = pct(0.99);
+  return HOT_OK;
+}
+
+hot_status hot_server_cancel(hot_server* S) {
+  if (!S) return HOT_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  // resident problems submitted so far stop after their current quantum
+  S->cancel_gen.fetch_add(1);
+  const double t = now_s();
+  for (const Request& r : S->queue) {  // queued ones finish now
+    Done d;
+    std::memset(&d.res, 0, sizeof(d.res));
+    d.res.status = HOT_E_CANCELLED;
+    d.tag = r.tag;
+    d.latency = t - r.t_submit;
+    S->done.push_back(d);
+    S->latencies.push_back(d.latency);
+    ++S->completed;
+  }
+  S->queue.clear();
+  S->cv.notify_all();
   return HOT_OK;
 }
 

@@ -26,7 +26,8 @@ EXPORTED = [
     "hot_solution_free", "hot_recover_plan", "hot_aat_solve", "hot_batch_submit",
     "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
     "hot_server_stats", "hot_server_destroy", "hot_server_drain", "hot_ctx_set_profiling",
-    "hot_ctx_profile_read", "hot_autotune", "hot_autotune_load",
+    "hot_ctx_profile_read", "hot_autotune", "hot_autotune_load", "hot_solution_anchor",
+    "hot_server_cancel",
 ]
 
 
@@ -47,7 +48,8 @@ class Result(C.Structure):
                 ("res_primal", C.c_double), ("res_dual", C.c_double), ("res_comp", C.c_double),
                 ("sigma", C.c_double), ("seconds", C.c_double), ("kkt_abs", C.c_double),
                 ("iters", C.c_int32),
-                ("restarts", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("restarts", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("feaserr", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -99,12 +101,12 @@ def lib():
     L.hot_autotune_load.argtypes = [vp, C.c_char_p]
     L.hot_ctx_set_profiling.argtypes = [vp, C.c_int]
     L.hot_ctx_profile_read.argtypes = [vp, C.POINTER(dbl)]
-    if hasattr(L, "hot_recover_plan"):
-        L.hot_recover_plan.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64),
-                                       C.POINTER(dbl)]
+    L.hot_recover_plan.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64),
+                                   C.POINTER(dbl)]
+    L.hot_solution_anchor.argtypes = [vp, vp, vp, vp, C.POINTER(dbl)]
+    L.hot_server_cancel.argtypes = [vp]
     for name in EXPORTED:
-        if hasattr(L, name):
-            getattr(L, name).restype = getattr(L, name).restype or C.c_int
+        getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.hot_ctx_destroy.restype = None
     L.hot_solution_free.restype = None
     L.hot_server_destroy.restype = None
@@ -310,6 +312,21 @@ class Solution:
             raise HotError(st, self.ctx.last_error())
         return xb, yb, zb, s
 
+    def anchor(self, stream=None):
+        """(s0 as a float64 CUDA tensor in paper order, info dict): the
+        Halpern anchor of the final epoch and the control values."""
+        import torch
+        m, n = self.m, self.n
+        s0 = torch.empty(m * m * n + m * n * n, dtype=torch.float64,
+                         device=torch.device("cuda", self.ctx.device))
+        info = (C.c_double * 4)()
+        st = lib().hot_solution_anchor(self.ctx.h, self.h, _stream_ptr(stream),
+                                       C.c_void_p(s0.data_ptr()), info)
+        if st != HOT_OK:
+            raise HotError(st, self.ctx.last_error())
+        return s0, {"k": int(info[0]), "lam": info[1], "sigma": info[2],
+                    "anchor": int(info[3])}
+
     def recover_plan(self, stream=None, capacity=None):
         """Algorithm 1 + marginal repair.  Returns (src, dst, mass, marg_err[4])."""
         import torch
@@ -363,6 +380,11 @@ class Server:
             self._alive.pop(d["tag"], None)
             out.append(d)
         return out
+
+    def cancel(self):
+        st = lib().hot_server_cancel(self.h)
+        if st != HOT_OK:
+            raise HotError(st, "cancel failed")
 
     def drain(self, timeout: float = 600.0):
         return lib().hot_server_drain(self.h, timeout)

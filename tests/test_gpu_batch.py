@@ -199,6 +199,30 @@ def test_batch_with_early_finishers_equals_alone():
             assert ra[key] == rb[key], (key, ra[key], rb[key])
 
 
+def test_batch_consecutive_compactions_equal_alone():
+    """Problems of each group stop on consecutive graphs (fixed iteration
+    counts 15, 35, 55 and 200), so the launch tables are rebuilt on three
+    consecutive polls while the previous upload may still be queued; every
+    result equals its solo solve bit for bit."""
+    need_gpu()
+    from paper_2408_00598_amd import hot
+    rng = np.random.default_rng(91)
+    per_group = [15, 15, 15, 15, 35, 35, 55, 200]
+    pairs, iters = [], []
+    for p in range(16):  # equal sizes: the two groups take every other pair
+        a, b = rng.uniform(0.1, 1, (12, 12)), rng.uniform(0.1, 1, (12, 12))
+        K = per_group[p // 2]
+        pairs.append((dev(a / a.sum()), dev(b / b.sum()), {"max_iter": K}))
+        iters.append(K)
+    c = ctx()
+    batch = c.batch_solve(pairs, flags=hot.HOT_FLAG_FIXED_ITERS)
+    for (a, b, kw), rb, K in zip(pairs, batch, iters):
+        ra, _ = c.solve(a, b, max_iter=K, flags=hot.HOT_FLAG_FIXED_ITERS)
+        assert rb["iters"] == K
+        for key in ("primal_obj", "dual_obj", "kkt", "feaserr", "iters", "status"):
+            assert ra[key] == rb[key], (key, ra[key], rb[key])
+
+
 def test_graph_replays_equal_direct_launches_bitwise(monkeypatch):
     """Iterations run as captured graphs, replayed many times with host reads
     of the control blocks and unrelated eager device work in between, give

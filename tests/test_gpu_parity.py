@@ -94,6 +94,8 @@ def test_converged_solve_fp64(oracle, m, n, tol):
     assert abs(res["primal_obj"] - ores["primal_obj"]) <= 1e-6 * abs(ores["primal_obj"])
     assert abs(res["kkt"] - ores["kkt"]) <= 1e-6 * ores["kkt"] + 1e-15
     assert res["kkt"] <= tol
+    # feasibility error of Sec. 4.1 (the negative part of x_bar dominates)
+    assert abs(res["feaserr"] - ores["feaserr"]) <= 1e-6 * ores["feaserr"] + 1e-15
 
 
 @pytest.mark.parametrize("m,n", [(8, 8), (32, 32), (20, 28)])
