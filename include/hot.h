@@ -222,6 +222,26 @@ void hot_solution_free(hot_solution *sol);
 hot_status hot_solution_anchor(hot_ctx *ctx, const hot_solution *sol,
                                hot_stream_t stream, double *s0, double *info);
 
+/* hot_solve without any allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Every device buffer of the solve is carved from one static
+ * device array of hot_noalloc_capacity() bytes (64 MiB) that each device
+ * holds until the process ends: a problem whose workspace does not fit
+ * (e.g. above 128 x 128 with FP32 streams or 96 x 96 in FP64) is rejected with
+ * HOT_E_INVALID and a message giving the bytes it needs.  The iteration runs
+ * on `stream` by direct launches (no graph, no event, no pinned buffer); the
+ * call returns when done.  Same kernels, launch shapes and order as
+ * hot_solve, so `res` and the iterate are bit-identical to it (res->seconds
+ * aside).  xbar (N doubles), ybar (3*m*n - 1 doubles): nullable caller-owned
+ * DEVICE buffers receiving the final x_bar and y_bar in the paper's ordering.
+ * The array keeps the last call's contents (what must start at zero is
+ * cleared by each call).  Calls on one context are serialised by its mutex;
+ * calls through different contexts on the same device share the array and
+ * race if they overlap, so such callers must serialise them. */
+hot_status hot_solve_noalloc(hot_ctx *ctx, const hot_problem *prob, hot_stream_t stream,
+                             double *xbar, double *ybar, hot_result *res);
+size_t hot_noalloc_capacity(void);
+
 /* Algorithm 1 on the clipped flows max(x_bar, 0) of `sol`, followed by the
  * marginal repair (rows above mu1 scaled down, then columns above mu2, then
  * the remaining deficits coupled north-west-corner in bin order).  Writes

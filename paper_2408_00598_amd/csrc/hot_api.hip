@@ -40,6 +40,7 @@ void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
                              double* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+void* static_scratch_init(int device, std::string& err);
 
 static int next_pow2(int v) {
   int p = 1;
@@ -320,15 +321,24 @@ void Workspace::release() {
   graph = nullptr;
   for (void* p : allocs) (void)hipFree(p);
   allocs.clear();
-  if (host_ctl) (void)hipHostFree(host_ctl);
+  if (host_ctl && host_ctl_vec.empty()) (void)hipHostFree(host_ctl);
   host_ctl = nullptr;
+  host_ctl_vec.clear();
   if (own_stream && stream) (void)hipStreamDestroy(stream);
   stream = nullptr;
 }
 
-// One device buffer.
+// One device buffer: hipMalloc, or the next 256-byte aligned piece of the
+// arena.  Past the arena's end nothing is handed out (the pointer is null)
+// but arena_used keeps counting, so the caller can report the size needed.
 hot_status Workspace::device_buffer(hot_ctx* ctx, void** p, size_t bytes) {
   bytes = std::max<size_t>(bytes, 256);
+  if (arena) {
+    const size_t off = (arena_used + 255) / 256 * 256;
+    arena_used = off + bytes;
+    *p = arena_used <= arena_bytes ? (void*)(arena + off) : nullptr;
+    return HOT_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -360,7 +370,7 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   const size_t n_si = std::max<size_t>(lay.sitems.size(), 1) * sizeof(SmallItem);
   const size_t n_bl = std::max<size_t>(lay.blocks.size(), 1) * sizeof(PBlock);
   const size_t n_sb = std::max<size_t>(lay.sblocks.size(), 1) * sizeof(PBlock);
-  if (lay.geo.size() > 1) {  // compacted launch tables (batches only)
+  if (lay.geo.size() > 1 && !arena) {  // compacted launch tables (batches only)
     if ((st = A((void**)&items_c, n_it)) != HOT_OK) return st;
     if ((st = A((void**)&sitems_c, n_si)) != HOT_OK) return st;
     if ((st = A((void**)&blocks_c, n_bl)) != HOT_OK) return st;
@@ -378,7 +388,18 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   if ((st = A((void**)&stats_d, lay.geo.size() * 2 * 8 * 8)) != HOT_OK) return st;
   if ((st = A((void**)&ptrs_d, lay.geo.size() * 2 * (sizeof(void*) + 8))) != HOT_OK) return st;
   if ((st = A((void**)&bytes_ctr, 256)) != HOT_OK) return st;
-  if (hipHostMalloc((void**)&host_ctl, lay.geo.size() * sizeof(PairCtl) * 2) != hipSuccess) {
+  if (arena) {
+    if (arena_used > arena_bytes) {
+      if (ctx)
+        ctx->err = "problem needs " + std::to_string(arena_used) +
+                   " bytes of device scratch, more than the " + std::to_string(arena_bytes) +
+                   " the no-alloc entry point holds";
+      return HOT_E_INVALID;
+    }
+    host_ctl_vec.assign(lay.geo.size() * 2, PairCtl());
+    host_ctl = host_ctl_vec.data();
+  } else if (hipHostMalloc((void**)&host_ctl, lay.geo.size() * sizeof(PairCtl) * 2) !=
+             hipSuccess) {
     host_ctl = nullptr;
     if (ctx) ctx->err = "hipHostMalloc failed";
     return HOT_E_NOMEM;
@@ -451,6 +472,10 @@ static hot_status validate_problem(hot_ctx* ctx, const hot_problem* p) {
 }
 
 namespace hot {
+
+hot_status validate_problem_public(hot_ctx* ctx, const hot_problem* p) {
+  return validate_problem(ctx, p);
+}
 
 // Validate histograms on the device, compute ||b|| and sigma, fill control
 // blocks, copy tables and clear the state.  Synchronises `st` once.
@@ -573,6 +598,12 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
     hot_status s1 = device_buffer(ctx, &xbuf, xb);
     if (s1 == HOT_OK) s1 = device_buffer(ctx, &ybuf, yb);
     if (s1 != HOT_OK) return s1;
+    if (arena && arena_used > arena_bytes) {
+      ctx->err = "problem needs " + std::to_string(arena_used) +
+                 " bytes of device scratch (sigma re-balancing included), more than the " +
+                 std::to_string(arena_bytes) + " the no-alloc entry point holds";
+      return HOT_E_INVALID;
+    }
     sbx = xbuf;
     abY = (double*)ybuf;
   }
@@ -753,6 +784,25 @@ hipError_t Workspace::poison_state(hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// No-alloc run: direct launches of kGraphIters iterations on st, then the
+// control blocks are copied back and st is synchronised; no graph, event or
+// pinned buffer.  Same kernels in the same order as run().
+hot_status Workspace::run_direct(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
+  const size_t np = lay.geo.size();
+  for (int64_t g = 0; g < max_graphs; ++g) {
+    for (int i = 0; i < kGraphIters; ++i) launch_iteration(args, i & 1, st);
+    HIPCK(hipGetLastError());
+    iterations_launched += kGraphIters;
+    HIPCK(hipMemcpyAsync(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    bool all_done = true;
+    for (size_t p = 0; p < np; ++p)
+      if (host_ctl[p].status == ST_RUNNING) all_done = false;
+    if (all_done) break;
+  }
+  return HOT_OK;
 }
 
 // Profiling run: direct launches, a hipEvent pair around every slab pass on
@@ -998,6 +1048,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.unroll = std::atoi(e) >= 2 ? 2 : 1;
   e = std::getenv("HOT_TEST_NAN_AFTER");
   if (e) c->nan_after = std::max(1, std::atoi(e));
+  // the no-alloc entry point's scratch array: its address on this device
+  c->scratch = static_scratch_init(device, c->scratch_err);
   *out = c;
   return HOT_OK;
 }

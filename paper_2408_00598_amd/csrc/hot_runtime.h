@@ -159,6 +159,12 @@ struct Workspace {
   int64_t prof_launches = 0;
   int64_t iterations_launched = 0;
 
+  // no-alloc solves: every device buffer is carved out of a caller-given
+  // arena (256-byte aligned) instead of hipMalloc, and the control blocks are
+  // read back into host_ctl_vec (no pinned allocation)
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  std::vector<PairCtl> host_ctl_vec;
   // test hook (HOT_TEST_NAN_AFTER): after this many graphs, write a NaN into
   // the first flow element of every state buffer; < 0 off
   int64_t nan_after = -1;
@@ -169,6 +175,9 @@ struct Workspace {
   hot_status alloc_all(hot_ctx* ctx);
   hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
   hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
+  // direct launches on st, a stream synchronisation per quantum, no graph,
+  // event or pinned buffer (the no-alloc entry point)
+  hot_status run_direct(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
   // Non-blocking pieces of run() for the server: capture the graph once,
   // launch one graph (kGraphIters iterations) + status copy + event.
   hot_status ensure_graph(hot_ctx* ctx, hipStream_t st);
@@ -203,6 +212,10 @@ struct hot_ctx {
   std::string err;
   hot::Tuning tune = hot::default_tuning();
   int64_t nan_after = -1;  // HOT_TEST_NAN_AFTER (failure-path tests only)
+  // device address of this device's no-alloc scratch array (null if its
+  // set-up failed; scratch_err says why)
+  void* scratch = nullptr;
+  std::string scratch_err;
   // measurement counters (hot_ctx_profile_read)
   bool profiling = false;
   double prof_seconds = 0, prof_launches = 0, prof_bytes = 0, iters_launched = 0;

@@ -27,7 +27,7 @@ EXPORTED = [
     "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
     "hot_server_stats", "hot_server_destroy", "hot_server_drain", "hot_ctx_set_profiling",
     "hot_ctx_profile_read", "hot_autotune", "hot_autotune_load", "hot_solution_anchor",
-    "hot_server_cancel",
+    "hot_solve_noalloc", "hot_noalloc_capacity", "hot_server_cancel",
 ]
 
 
@@ -104,6 +104,9 @@ def lib():
     L.hot_recover_plan.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64),
                                    C.POINTER(dbl)]
     L.hot_solution_anchor.argtypes = [vp, vp, vp, vp, C.POINTER(dbl)]
+    L.hot_solve_noalloc.argtypes = [vp, C.POINTER(Problem), vp, vp, vp, C.POINTER(Result)]
+    L.hot_noalloc_capacity.argtypes = []
+    L.hot_noalloc_capacity.restype = C.c_size_t
     L.hot_server_cancel.argtypes = [vp]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
@@ -213,6 +216,27 @@ class Context:
         out["return_status"] = st
         solution = Solution(self, sol, prob.m, prob.n, (mu1, mu2)) if keep and sol else None
         return out, solution
+
+    def solve_noalloc(self, mu1, mu2, outputs=True, stream=None, **kw):
+        """Run hot_solve_noalloc; returns (result dict, xbar, ybar) with the
+        final iterate in caller-owned tensors (None unless outputs)."""
+        import torch
+        prob = self.problem(mu1, mu2, **kw)
+        m, n = prob.m, prob.n
+        xb = yb = None
+        if outputs:
+            xb = torch.empty(m * m * n + m * n * n, dtype=torch.float64, device=mu1.device)
+            yb = torch.empty(3 * m * n - 1, dtype=torch.float64, device=mu1.device)
+        res = Result()
+        st = lib().hot_solve_noalloc(self.h, C.byref(prob), _stream_ptr(stream),
+                                     None if xb is None else C.c_void_p(xb.data_ptr()),
+                                     None if yb is None else C.c_void_p(yb.data_ptr()),
+                                     C.byref(res))
+        if st not in (HOT_OK, HOT_E_NOT_CONVERGED):
+            raise HotError(st, self.last_error())
+        out = res.as_dict()
+        out["return_status"] = st
+        return out, xb, yb
 
     def aat_solve(self, m, n, R, stream=None):
         import torch
