@@ -40,6 +40,8 @@ void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
                              double* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+void launch_finalize(const LaunchArgs& a, const SlabItem* items_all, int nitems_all, int npairs,
+                     hipStream_t st);
 void* static_scratch_init(int device, std::string& err);
 
 static int next_pow2(int v) {
@@ -761,7 +763,9 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
   (void)hipEventDestroy(ev[1]);
   if (result == HOT_OK) {
     // the final control blocks: after whole graphs the latest copy is ctl[0]
-    e = hipMemcpy(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost);
+    e = finalize(st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
       ctx->err = std::string("status copy failed: ") + hipGetErrorString(e);
       result = HOT_E_DEVICE;
@@ -802,7 +806,15 @@ hot_status Workspace::run_direct(hot_ctx* ctx, hipStream_t st, int64_t max_graph
       if (host_ctl[p].status == ST_RUNNING) all_done = false;
     if (all_done) break;
   }
+  HIPCK(finalize(st));
+  HIPCK(hipMemcpyAsync(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
   return HOT_OK;
+}
+
+hipError_t Workspace::finalize(hipStream_t st) {
+  launch_finalize(args, items_d, (int)lay.items.size(), (int)lay.geo.size(), st);
+  return hipGetLastError();
 }
 
 // Profiling run: direct launches, a hipEvent pair around every slab pass on
@@ -836,6 +848,9 @@ hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_gra
     if (all_done) break;
   }
   for (auto& e : evs) (void)hipEventDestroy(e);
+  HIPCK(finalize(st));
+  HIPCK(hipMemcpyAsync(host_ctl, ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
   return result;
 }
 
@@ -1271,8 +1286,11 @@ hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Worksp
       if (t.ev[q]) (void)hipEventDestroy(t.ev[q]);
     if (result == HOT_OK) {
       // after whole graphs the latest control blocks are ctl[0]
-      e = hipMemcpy(t.ws->host_ctl, t.ws->ctl_d, t.ws->lay.geo.size() * sizeof(PairCtl),
-                    hipMemcpyDeviceToHost);
+      e = t.ws->finalize(t.ws->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(t.ws->stream);
+      if (e == hipSuccess)
+        e = hipMemcpy(t.ws->host_ctl, t.ws->ctl_d, t.ws->lay.geo.size() * sizeof(PairCtl),
+                      hipMemcpyDeviceToHost);
       if (e != hipSuccess) {
         ctx->err = std::string("status copy failed: ") + hipGetErrorString(e);
         result = HOT_E_DEVICE;

@@ -47,14 +47,12 @@ enum PairStatus : int32_t {
 };
 
 // per-item partial indices (slab pass, check mode)
-// (KI_NEG: ||min(x_bar, 0)||^2, the first term of the feasibility error of
-// the experiments)
+// (after the solve, the finalize pass reuses slots KI_DX and KI_NEG for
+// ||x_bar||^2 and ||min(x_bar, 0)||^2 of the final iterate)
 enum KItem : int { KI_DUAL = 0, KI_COMP, KI_XX, KI_ZZ, KI_CX, KI_FP, KI_DX, KI_NEG };
 // per-block partial indices (pair reduce, check mode)
-enum KPart : int {
-  KP_DUAL = 0, KP_COMP, KP_XX, KP_ZZ, KP_CX, KP_FP, KP_DX, KP_PRIM, KP_BY, KP_DY, KP_NEG
-};
-constexpr int kNKP = 11;  // partials per reduce block in use (of kKP slots)
+enum KPart : int { KP_DUAL = 0, KP_COMP, KP_XX, KP_ZZ, KP_CX, KP_FP, KP_DX, KP_PRIM, KP_BY, KP_DY };
+constexpr int kNKP = 10;  // partials per reduce block in use (of kKP slots)
 
 struct FamGeo {
   int32_t L;       // slab side

@@ -262,14 +262,12 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     if (mode != MODE_CHECK) continue;
 
     // ---- check pass: KKT partials of w_bar^k -------------------------------
-    double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double part[kNKP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     {
       const int i0 = G.item0 + slot * G.ipb;
       const int i1 = min(G.item0 + G.nitem, i0 + G.ipb);
-      for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG) {
+      for (int it = i0 + (int)threadIdx.x; it < i1; it += kWG)
         for (int q = 0; q <= KI_DX; ++q) part[q] += kitem[(int64_t)it * kKI + q];
-        part[KP_NEG] += kitem[(int64_t)it * kKI + KI_NEG];
-      }
     }
     if (su && has_slab) {
       // ||A^T (y_bar - Y)||^2 over this slab: A^T y is alpha_p + beta_q on it,
@@ -395,7 +393,6 @@ __device__ void decide(const PairGeo& G, const PairCtl& c, const double* acc, Pa
       nx.res_p = sqrt(acc[KP_PRIM]) / (1.0 + G.norm_b);
       nx.kkt = fmax(nx.res_d, fmax(nx.res_c, nx.res_p));
       nx.kkt_abs = sqrt(acc[KP_PRIM] + acc[KP_COMP] + acc[KP_DUAL]);
-      nx.feaserr = fmax(sqrt(acc[KP_NEG]) / (1.0 + nx2), nx.res_p);
       const double crit = (c.flags & 8) ? nx.kkt_abs : nx.kkt;
       nx.pobj = acc[KP_CX];
       nx.dobj = acc[KP_BY];
@@ -802,6 +799,72 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
+// Finalize (once per solve, after the last check): the feasibility error of
+// the experiments, max(||min(x_bar, 0)|| / (1 + ||x_bar||), res_primal), of
+// the final iterate x_bar = sigma (s - g).  A reporting metric only, so it is
+// kept out of the slab pass (an eighth check accumulator there cost the
+// streaming kernel 20 VGPRs and a wave per SIMD).  One workgroup per slab
+// item writes the item's (||x_bar||^2, ||x_bar^-||^2) into its partial slots;
+// one workgroup per problem adds them in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_feas_items(const SlabItem* __restrict__ items,
+                                                    const PairGeo* __restrict__ geo,
+                                                    const PairCtl* __restrict__ ctl,
+                                                    const T* __restrict__ sb0,
+                                                    const T* __restrict__ sb1,
+                                                    const T* __restrict__ sb2,
+                                                    const double* __restrict__ ab,
+                                                    double* __restrict__ kitem) {
+  __shared__ double red[4];
+  const SlabItem itm = items[blockIdx.x];
+  const PairCtl* cp = ctl + itm.pair;
+  const FamGeo F = geo[itm.pair].f[itm.fam];
+  const int L = F.L;
+  const T* s = pick<const T>(sb0, sb1, sb2, cp->src) + F.soff + (int64_t)itm.slab * L * F.P;
+  const double* alpha = ab + F.aboff + (int64_t)itm.slab * 2 * L;
+  const double* beta = alpha + L;
+  const double* X = fam_x(ab, F);
+  const double sigma = cp->sigma;
+  const int r0 = itm.chunk * F.rpc, r1 = min(L, r0 + F.rpc);
+  const int64_t cnt = (int64_t)(r1 - r0) * L;
+  double xx = 0.0, neg = 0.0;
+  for (int64_t e = threadIdx.x; e < cnt; e += kWG) {
+    const int p = r0 + (int)(e / L), q = (int)(e % L);
+    const double d = X[p] - X[q];
+    const double g = d * d - (alpha[p] + beta[q]);
+    const double xb = sigma * ((double)s[(int64_t)p * F.P + q] - g);
+    const double xn = fmin(xb, 0.0);
+    xx += xb * xb;
+    neg += xn * xn;
+  }
+  xx = block_sum(xx, red);
+  neg = block_sum(neg, red);
+  if (threadIdx.x == 0) {
+    kitem[(int64_t)itm.kslot * kKI + KI_DX] = xx;
+    kitem[(int64_t)itm.kslot * kKI + KI_NEG] = neg;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_feas_pairs(const PairGeo* __restrict__ geo,
+                                                    PairCtl* __restrict__ ctl,
+                                                    const double* __restrict__ kitem) {
+  __shared__ double red[4];
+  const PairGeo G = geo[blockIdx.x];
+  double xx = 0.0, neg = 0.0;
+  for (int it = G.item0 + (int)threadIdx.x; it < G.item0 + G.nitem; it += kWG) {
+    xx += kitem[(int64_t)it * kKI + KI_DX];
+    neg += kitem[(int64_t)it * kKI + KI_NEG];
+  }
+  xx = block_sum(xx, red);
+  neg = block_sum(neg, red);
+  if (threadIdx.x == 0) {
+    PairCtl* c = ctl + blockIdx.x;
+    c->feaserr = fmax(sqrt(neg) / (1.0 + sqrt(xx)), c->res_p);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Setup and export helpers.
 // ---------------------------------------------------------------------------
 
@@ -1055,6 +1118,22 @@ void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
                              double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_hist_stats_multi, dim3(count), dim3(kWG), 0, st, ptrs, lens, out);
+}
+
+// Finalize every problem of a workspace (full launch tables, control blocks
+// ctl[0], which hold the final state after whole graphs).
+void launch_finalize(const LaunchArgs& a, const SlabItem* items_all, int nitems_all, int npairs,
+                     hipStream_t st) {
+  if (nitems_all < 1 || npairs < 1) return;
+  if (a.fp32)
+    hipLaunchKernelGGL(k_feas_items<float>, dim3(nitems_all), dim3(kWG), 0, st, items_all, a.geo,
+                       a.ctl[0], (const float*)a.sb[0], (const float*)a.sb[1],
+                       (const float*)a.sb[2], a.ab, a.kitem);
+  else
+    hipLaunchKernelGGL(k_feas_items<double>, dim3(nitems_all), dim3(kWG), 0, st, items_all,
+                       a.geo, a.ctl[0], (const double*)a.sb[0], (const double*)a.sb[1],
+                       (const double*)a.sb[2], a.ab, a.kitem);
+  hipLaunchKernelGGL(k_feas_pairs, dim3(npairs), dim3(kWG), 0, st, a.geo, a.ctl[0], a.kitem);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t st) {

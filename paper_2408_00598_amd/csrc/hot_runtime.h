@@ -183,6 +183,9 @@ struct Workspace {
   hot_status ensure_graph(hot_ctx* ctx, hipStream_t st);
   hipError_t launch_quantum(hipStream_t st);
   hipError_t poison_state(hipStream_t st);
+  // after the last graph: the feasibility error of every problem's final
+  // iterate into ctl[0] (on st; copy the control blocks after it)
+  hipError_t finalize(hipStream_t st);
   hipEvent_t quantum_event = nullptr;
   hot_status run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
   void fill_result(int p, hot_result* r, double seconds) const;

@@ -186,8 +186,11 @@ static void server_loop(hot_server* S) {
           continue;
         }
       }
-      // finished (or failed): the last copied control block is final once
-      // the stream is idle
+      // finished (or failed): the final control block (with the finalize
+      // pass's metrics) once the stream is idle
+      if (e == hipSuccess && sl.ws->finalize(sl.ws->stream) == hipSuccess)
+        (void)hipMemcpyAsync(sl.ws->host_ctl, sl.ws->ctl_d, sizeof(PairCtl),
+                             hipMemcpyDeviceToHost, sl.ws->stream);
       (void)hipStreamSynchronize(sl.ws->stream);
       Done d;
       const double t = now_s();

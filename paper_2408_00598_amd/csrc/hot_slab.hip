@@ -60,7 +60,7 @@ __device__ __forceinline__ void slab_rows(const SlabCtx& x, const T* __restrict_
                                  const double* __restrict__ alpha, const double* __restrict__ bl,
                                  const double* __restrict__ lx,
                                  double (&colacc)[MAXVPL][VecT<T>::W], double* __restrict__ rowsum,
-                                 double (&kk)[kKI]) {
+                                 double (&kk)[7]) {
   constexpr int W = VecT<T>::W;
   typedef typename VecT<T>::type VT;
   constexpr bool RDX = SU && MODE == MODE_CHECK;    // read X
@@ -126,10 +126,8 @@ __device__ __forceinline__ void slab_rows(const SlabCtx& x, const T* __restrict_
                 const double dr = zb - g;
                 const double mn = fmin(xb, zb);
                 const double fr = s - sh;
-                const double xn = fmin(xb, 0.0);
                 kk[KI_DUAL] += ok ? dr * dr : 0.0;
                 kk[KI_COMP] += ok ? mn * mn : 0.0;
-                kk[KI_NEG] += ok ? xn * xn : 0.0;
                 kk[KI_XX] += ok ? xb * xb : 0.0;
                 kk[KI_ZZ] += ok ? zb * zb : 0.0;
                 kk[KI_CX] += ok ? d * d * xb : 0.0;
@@ -237,7 +235,7 @@ __device__ __forceinline__ void slab_item(
   for (int v = 0; v < MAXVPL; ++v)
 #pragma unroll
     for (int e = 0; e < W; ++e) colacc[v][e] = 0.0;
-  double kk[kKI] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double kk[7] = {0, 0, 0, 0, 0, 0, 0};
   // check and restart rows: one row step at a time; plain rows: the
   // launch's unroll and store kind
   constexpr int UH = HEAVY == 2 ? 1 : U;
@@ -304,18 +302,17 @@ __device__ __forceinline__ void slab_item(
   if (HEAVY && mode == MODE_CHECK) {
     // all partials at once: wave sums, one barrier, then the fixed order
     // (w0 + w1) + (w2 + w3) per partial
-    // (KI_DX stays zero without sigma re-balancing)
     double* ko = kitem + (int64_t)itm.kslot * kKI;
+    const int nq = su ? 7 : 6;
 #pragma unroll
-    for (int q = 0; q < kKI; ++q) {
-      if (q == KI_DX && !su) continue;
+    for (int q = 0; q < 7; ++q) {
       const double v = wave_sum(kk[q]);
-      if (x.lane == 0) red[x.wave * 8 + q] = v;
+      if (q < nq && x.lane == 0) red[x.wave * 8 + q] = v;
     }
     __syncthreads();
-    if ((int)threadIdx.x < kKI) {
+    if ((int)threadIdx.x < nq) {
       const int q = threadIdx.x;
-      ko[q] = (q == KI_DX && !su) ? 0.0 : (red[q] + red[8 + q]) + (red[16 + q] + red[24 + q]);
+      ko[q] = (red[q] + red[8 + q]) + (red[16 + q] + red[24 + q]);
     }
   }
 }
