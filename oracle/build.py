@@ -14,14 +14,20 @@ LIB_OMP = os.path.join(OUT_DIR, "libhot_oracle_omp.so")  # same source, -fopenmp
 SRC = os.path.join(HERE, "hot_oracle.c")
 
 
-def build(openmp: bool = False, quiet: bool = True) -> str:
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+            "-fno-omit-frame-pointer", "-g"]
+
+
+def build(openmp: bool = False, quiet: bool = True, sanitize_to: str = "") -> str:
     """The serial oracle, or (openmp) the same source with its independent
-    loops on several threads, for multi-core timing only."""
+    loops on several threads, for multi-core timing only.  sanitize_to: build
+    the serial oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    into this path instead (the sanitizer test loads it)."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    out = LIB_OMP if openmp else LIB
+    out = sanitize_to or (LIB_OMP if openmp else LIB)
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-fno-fast-math", *(["-fopenmp"] if openmp else []), SRC, "-o", out + ".tmp",
-           "-lm"]
+           "-fno-fast-math", *(["-fopenmp"] if openmp else []),
+           *(SANITIZE if sanitize_to else []), SRC, "-o", out + ".tmp", "-lm"]
     subprocess.run(cmd, check=True, capture_output=quiet)
     os.replace(out + ".tmp", out)
     return out

@@ -6,6 +6,8 @@ the paper's vectorisation (Sec. 2.1): x = [f1; f2] with f1_{i,k,j} at
 (j*m+k)*m+i and f2_{k,j,l} at m*m*n + (l*n+j)*m+k.
 """
 import ctypes as C
+import os
+
 import numpy as np
 
 from .build import ensure_built
@@ -42,7 +44,10 @@ def lib(openmp=False):
     """The serial oracle, or its OpenMP build (same source, identical results;
     for multi-core timing)."""
     if openmp not in _libs:
-        L = C.CDLL(ensure_built(openmp))
+        # HOT_ORACLE_LIB: a build of the same source to load instead (the
+        # sanitizer test's AddressSanitizer build)
+        path = os.environ.get("HOT_ORACLE_LIB") if not openmp else None
+        L = C.CDLL(path or ensure_built(openmp))
         L.or_dims.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.or_cost.argtypes = [C.c_int32, C.c_int32, D]
         L.or_cost_xy.argtypes = [C.c_int32, C.c_int32, D, D, D]

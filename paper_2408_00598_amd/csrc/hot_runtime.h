@@ -52,6 +52,8 @@ struct Tuning {
 };
 Tuning default_tuning();
 int size_class(int64_t v);  // floor(log2(v)) for v >= 1
+// ||c||^2 of one slab's cost on the uniform grid: sum_{p,q} (p-q)^4 (exact)
+double slab_cost_sq(int L);
 inline Tuning::Key tune_key(int fp32, int64_t elems, int npairs) {
   return Tuning::Key{fp32, size_class(elems), size_class(npairs)};
 }
