@@ -6,21 +6,35 @@
 // row, f2_{k,j,l} for l = 1..n, each step taking the smaller remaining
 // amount.  That greedy rule is the north-west-corner coupling of the two
 // sequences: with P_i, Q_l their running totals, source i and target l
-// exchange the overlap of (P_{i-1}, P_i] and (Q_{l-1}, Q_l].  One wave owns
-// one bin: it stages both running totals in LDS (FP64).  The entries are the
-// segments between consecutive values of the merged totals; the wave takes
-// them 64 at a time (merge-path search per lane, a ballot to skip empty
-// ones), so both the count and the write pass are balanced across lanes and
-// the write is contiguous.  The scaled marginal passes walk each source's
-// (or target's) overlaps from a binary-searched start.  Entries are counted,
-// offsets come from a scan, and the write pass emits them in a fixed order:
-// bins in (k*n + j) order, then source i, then target l.  The flows are the
-// clipped max(x_bar, 0) of the solution.
+// exchange the overlap of (P_{i-1}, P_i] and (Q_{l-1}, Q_l].  The flows are
+// the clipped max(x_bar, 0) of the solution, computed on the fly from the
+// solver's state (x_bar = sigma (s - g), as the export computes it): nothing
+// flow-sized is written.
+//
+// A bin's inputs are one row of each family's slabs: row k of F1^(j)
+// (sources) and row j of F2^(k) (targets), both contiguous.  One wave takes a
+// bin at a time: lanes own sources (or targets) i = lane + 64 r, the running
+// totals come from a fixed-order wave scan per 64-element round (with a
+// running maximum, exact, so that they never decrease), and the side that is
+// searched sits in the wave's LDS.  Three passes over the bins, each needing
+// the previous one's global result:
+//   rows:  raw matched amount of every source (clipped at the bin's target
+//          total) -> row marginals r of the plan -> row scale factors;
+//   cols:  per target, the overlaps scaled by the row factors, and the raw
+//          matched amount (clipped at the source total) -> column marginals
+//          after the row scaling -> column scale factors; entries per bin;
+//   write: per source, its overlaps in target order, scaled by both
+//          factors, written at the bin's offset (bins in (k*n + j) order,
+//          then source i, then target l) -> row marginals after scaling.
+// A wave takes G consecutive bins of one slab (G from the problem size) and
+// keeps its marginal contributions in registers; the waves' partials are
+// added in a fixed order by a separate pass, so results are deterministic.
 //
 // Repair (the algorithm assumes an exactly optimal, feasible flow): rows
 // whose total exceeds mu1 are scaled down, then columns above mu2, and the
 // remaining row and column deficits are coupled north-west-corner in bin
-// order.  All marginals are computed with fixed-order sums (no atomics).
+// order (a merge path over the two running-total arrays).  All marginals are
+// computed with fixed-order sums (no atomics).
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -34,6 +48,8 @@ namespace hot {
 namespace {
 
 constexpr int kScanBlock = 1024;  // elements per block of the scans
+constexpr int kRecWaves = 4;      // waves (bin units) per workgroup of the bin passes
+constexpr int kNwSpan = 16;       // merged breakpoints per thread of the deficit coupling
 
 __device__ inline double wave_sum_r(double v) {
 #pragma unroll
@@ -41,259 +57,580 @@ __device__ inline double wave_sum_r(double v) {
   return v;
 }
 
-// Clipped flows in unpadded slab layout: F1^(j)[k][i] at j*m*m + k*m + i,
-// F2^(k)[j][l] at m*m*n + k*n*n + j*n + l.
+// LDS written by lanes of a wave and read by other lanes of the same wave
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Clipped flow of one element: max(sigma (s - g), 0) with
+// g = (X_p - X_q)^2 - alpha_p - beta_q, the arithmetic of the export; on the
+// uniform grid X_p - X_q = p - q exactly.
+__device__ inline double clip_flow(double sv, double d, double ap, double bq, double sigma) {
+  const double g = d * d - ap - bq;
+  const double x = sigma * (sv - g);
+  return x > 0.0 ? x : 0.0;
+}
+
+// ---- wave primitives (DPP: no LDS round trip) ------------------------------
+template <int CTRL, int RM = 0xf>
+__device__ inline double dpp_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, int RM = 0xf>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, RM, 0xf, false);
+}
+// inclusive sum over lanes 0..t (row_shr 1, 2, 4, 8 in each 16-lane row, then
+// row_bcast:15 and row_bcast:31 across rows); fixed order
+__device__ inline double wave_incl_sum(double v) {
+  v += dpp_d<0x111>(v);
+  v += dpp_d<0x112>(v);
+  v += dpp_d<0x114>(v);
+  v += dpp_d<0x118>(v);
+  v += dpp_d<0x142, 0xa>(v);
+  v += dpp_d<0x143, 0xc>(v);
+  return v;
+}
+__device__ inline int wave_incl_sum_i(int v) {
+  v += dpp_i<0x111>(v);
+  v += dpp_i<0x112>(v);
+  v += dpp_i<0x114>(v);
+  v += dpp_i<0x118>(v);
+  v += dpp_i<0x142, 0xa>(v);
+  v += dpp_i<0x143, 0xc>(v);
+  return v;
+}
+// inclusive maximum over lanes 0..t of v >= 0 (the shifted-in zeros are no-ops)
+__device__ inline double wave_incl_max(double v) {
+  v = fmax(v, dpp_d<0x111>(v));
+  v = fmax(v, dpp_d<0x112>(v));
+  v = fmax(v, dpp_d<0x114>(v));
+  v = fmax(v, dpp_d<0x118>(v));
+  v = fmax(v, dpp_d<0x142, 0xa>(v));
+  v = fmax(v, dpp_d<0x143, 0xc>(v));
+  return v;
+}
+// the value of lane t-1 (0 in lane 0): wave_shr:1
+__device__ inline double wave_prev(double v) { return dpp_d<0x138>(v); }
+__device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ inline double lane63(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// ---- a bin row, lane-blocked: lane t holds elements t B + b, b < B ---------
 template <typename T>
-__global__ void k_clip_flows(const PairGeo* __restrict__ geo, const PairCtl* __restrict__ ctl,
-                             int pair, const T* __restrict__ sb0, const T* __restrict__ sb1,
-                             const T* __restrict__ sb2, const double* __restrict__ ab,
-                             double* __restrict__ w) {
-  const PairGeo G = geo[pair];
-  const PairCtl c = ctl[pair];
-  const int m = G.m, n = G.n;
-  const int64_t N1 = (int64_t)m * m * n, N = N1 + (int64_t)m * n * n;
-  const T* s = c.src == 0 ? sb0 : (c.src == 1 ? sb1 : sb2);
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int fam = e < N1 ? 0 : 1;
-    const FamGeo F = G.f[fam];
-    const int64_t r = fam == 0 ? e : e - N1;
-    const int L = F.L;
-    const int q = (int)(r % L);
-    const int64_t t = r / L;
-    const int p = (int)(t % L);
-    const int slab = (int)(t / L);
-    const double sv = (double)s[F.soff + ((int64_t)slab * L + p) * F.P + q];
-    const double* al = ab + F.aboff + (int64_t)slab * 2 * L;
-    const double* X = fam_x(ab, F);
-    const double d = X[p] - X[q];
-    const double g = d * d - al[p] - al[L + q];
-    const double x = c.sigma * (sv - g);
-    w[e] = x > 0.0 ? x : 0.0;
-  }
-}
-
-// LDS running totals of one bin: P[0..m] over sources, Q[0..n] over targets.
-__device__ inline void stage_prefix(const double* __restrict__ src, int len, double* out,
-                                    int lane) {
-  for (int t = lane; t < len; t += 64) out[1 + t] = src[t];
-  if (lane == 0) out[0] = 0.0;
-  __syncthreads();
-  const int chunk = (len + 63) / 64;
-  const int b0 = min(len, lane * chunk), b1 = min(len, b0 + chunk);
-  double loc = 0.0;
-  for (int t = b0; t < b1; ++t) loc += out[1 + t];
-  double incl = loc;
-  for (int off = 1; off < 64; off <<= 1) {
-    const double v = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += v;
-  }
-  double run = __shfl_up(incl, 1, 64);
-  if (lane == 0) run = 0.0;
-  __syncthreads();
-  for (int t = b0; t < b1; ++t) {
-    run += out[1 + t];
-    out[1 + t] = run;
-  }
-  __syncthreads();
-  // The lanes' totals are rounded in different orders, so where flows are
-  // zero a total can sit a rounding step below its predecessor.  A running
-  // maximum (exact in any order) makes the totals nondecreasing, as the
-  // searches over them assume.
-  double mx = 0.0;
-  for (int t = b0; t < b1; ++t) mx = fmax(mx, out[1 + t]);
-  for (int off = 1; off < 64; off <<= 1) {
-    const double v = __shfl_up(mx, off, 64);
-    if (lane >= off) mx = fmax(mx, v);
-  }
-  double rm = __shfl_up(mx, 1, 64);
-  if (lane == 0) rm = 0.0;
-  for (int t = b0; t < b1; ++t) {
-    rm = fmax(rm, out[1 + t]);
-    out[1 + t] = rm;
-  }
-  __syncthreads();
-}
-
-// smallest index l in [0, n) with Q[l+1] > v, or n
-__device__ inline int first_above(const double* Q, int n, double v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (Q[mid + 1] > v) hi = mid; else lo = mid + 1;
-  }
-  return lo;
-}
-
-// smallest index l in [0, n] with l == n or Q[l] >= v (Q nondecreasing)
-__device__ inline int count_below(const double* Q, int n, double v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (Q[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-enum RecPass { PASS_COUNT = 0, PASS_COLSCALED = 1, PASS_BOTHSCALED = 2, PASS_WRITE = 3 };
-
-// The bin's coupling entries in order, 64 candidates per call.  Candidate t
-// (t < m + n) is the segment (e_{t-1}, e_t] between consecutive values of the
-// merged running totals {P[1..m]} and {Q[1..n]} (e_{-1} = 0); it is an entry
-// when it has positive length and lies inside both totals: then it is the
-// overlap of source i = #{P[1..m] <= e_{t-1}} and target l likewise, exactly
-// min(P[i+1], Q[l+1]) - max(P[i], Q[l]).  Entries come out in the order of
-// Algorithm 1's walk (source, then target), and a wave writes them to
-// consecutive positions.  `prev` carries e of the previous chunk's last lane.
-struct Seg {
-  bool ok;
-  int i, l;
-  double lo, hi;  // the segment (lo, hi]
+struct RowRef {
+  const T* s;
+  const double* beta;
+  const double* X;
+  double xp, ap;
+  int p;
 };
-__device__ inline Seg bin_segment(const double* P, const double* Q, int m, int n, int t,
-                                  int lane, double& prev) {
-  double e = 0.0;
-  if (t < m + n) {
-    // merge path: a of the k = t + 1 smallest come from P (ties: P first)
-    const int k = t + 1;
-    int lo = max(0, k - n), hi = min(k, m);
-    while (lo < hi) {
-      const int a = (lo + hi) >> 1;
-      if (P[a + 1] <= Q[k - a]) lo = a + 1; else hi = a;
-    }
-    e = fmax(P[lo], Q[k - lo]);
-  }
-  double u = __shfl_up(e, 1, 64);
-  if (lane == 0) u = prev;
-  prev = __shfl(e, 63, 64);
-  Seg sg;
-  sg.ok = false;
-  sg.i = m;
-  sg.l = n;
-  sg.lo = u;
-  sg.hi = e;
-  if (t < m + n && e > u) {
-    sg.i = first_above(P, m, u);
-    sg.l = first_above(Q, n, u);
-    sg.ok = sg.i < m && sg.l < n;
-  }
-  return sg;
+
+template <typename T>
+__device__ inline RowRef<T> row_ref(const T* s, const double* ab, const FamGeo& F, int slab,
+                                    int p) {
+  RowRef<T> r;
+  const int L = F.L;
+  r.s = s + F.soff + ((int64_t)slab * L + p) * F.P;
+  const double* al = ab + F.aboff + (int64_t)slab * 2 * L;
+  r.beta = al + L;
+  r.X = fam_x(ab, F);
+  r.xp = r.X[p];
+  r.ap = al[p];
+  r.p = p;
+  return r;
 }
 
-// One wave per bin (k, j), item = k*n + j.
-template <int PASS>
-__global__ __launch_bounds__(64) void k_rec_bin(int m, int n, const double* __restrict__ w,
-                                                double* __restrict__ mt,
-                                                long long* __restrict__ counts,
-                                                const long long* __restrict__ offsets,
-                                                const double* __restrict__ rho_r,
-                                                const double* __restrict__ rho_c,
-                                                int32_t* __restrict__ osrc,
-                                                int32_t* __restrict__ odst,
-                                                double* __restrict__ omass) {
+// The row's clipped flows of the lane's block (0 past L).  BPRE: beta from
+// bpre[] (preloaded for the slab a unit keeps), else from memory.  UNI:
+// uniform grid.
+template <typename T, int MAXB, bool UNI, bool BPRE>
+__device__ inline void load_row(const RowRef<T>& row, int L, int B, double sigma,
+                                const double* bpre, int lane, double (&v)[MAXB]) {
+  const int q0 = lane * B;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int q = q0 + b;
+    v[b] = 0.0;
+    if (b < B && q < L) {
+      const double d = UNI ? (double)(row.p - q) : row.xp - row.X[q];
+      const double bq = BPRE ? bpre[b] : row.beta[q];
+      v[b] = clip_flow((double)row.s[q], d, row.ap, bq, sigma);
+    }
+  }
+}
+
+template <int MAXB>
+__device__ inline void preload(const double* src, int L, int B, int lane, double (&out)[MAXB]) {
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int q = lane * B + b;
+    out[b] = (b < B && q < L) ? src[q] : 0.0;
+  }
+}
+
+// Running totals of the lane's block: hi[b] the total through element t B + b,
+// lo0 the total before the block; returns the grand total.  Sequential sums
+// in the lane, a fixed-order scan of the block totals, then a running maximum
+// across lanes (exact), so the totals never decrease, as the searches over
+// them assume.  Every pass computes a row's totals with this one function,
+// so all passes see the same values bit for bit.
+// The grand total is the value at the row's last element: lanes past the
+// row (whose tree-ordered sums of zeros could round above it) take no part
+// in the maximum.
+template <int MAXB>
+__device__ inline double block_totals(const double (&v)[MAXB], int L, int B, int lane,
+                                      double (&hi)[MAXB], double& lo0) {
+  double s = 0.0;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    s += v[b];
+    hi[b] = s;
+  }
+  const double excl = wave_prev(wave_incl_sum(s));
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) hi[b] = excl + hi[b];
+  const double mx = wave_incl_max(lane * B < L ? hi[MAXB - 1] : 0.0);
+  const double M = wave_prev(mx);
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) hi[b] = fmax(hi[b], M);
+  lo0 = M;
+  return lane63(mx);
+}
+
+// Plain running sums of the lane's block (no monotonicity needed): out[b]
+// the sum through element t B + b.
+template <int MAXB>
+__device__ inline void block_sums(const double (&v)[MAXB], double (&out)[MAXB]) {
+  double s = 0.0;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    s += v[b];
+    out[b] = s;
+  }
+  const double excl = wave_prev(wave_incl_sum(s));
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) out[b] = excl + out[b];
+}
+
+// lane block's totals into LDS out[1 + q] (out[0] = 0)
+template <int MAXB>
+__device__ inline void stage(const double (&hi)[MAXB], int L, int B, double* out, int lane) {
+  if (lane == 0) out[0] = 0.0;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int q = lane * B + b;
+    if (b < B && q < L) out[1 + q] = hi[b];
+  }
+}
+
+// smallest index i in [0, n) with P[i+1] >= v, or n
+__device__ inline int first_at_least(const double* P, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (P[mid + 1] >= v) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Cumulative weighted amount at t >= 0 over running totals P[0..n] (P[0] =
+// 0) with F[i] = sum over the intervals before i of their amount times w:
+// F[i] + (t - P[i]) w_i on the interval (P[i], P[i+1]] containing t, F[n]
+// past the total.  `i` is a cursor (smallest i with P[i+1] >= t): callers
+// evaluate nondecreasing t, so it only moves forward.
+// The cursor moves by galloping (steps 1, 2, 4, .. then a binary search), so
+// a lane whose values span many intervals of the other side (mass
+// concentrated in a few bins) pays a logarithm, not a walk.
+__device__ inline int advance(const double* P, int n, int i, double t) {
+  if (i >= n || P[i + 1] >= t) return i;
+  int cur = i, step = 1, hi = n;  // P[cur+1] < t
+  for (;;) {
+    const int nx = cur + step;
+    if (nx >= n) break;
+    if (P[nx + 1] >= t) {
+      hi = nx;
+      break;
+    }
+    cur = nx;
+    step <<= 1;
+  }
+  int lo = cur + 1;  // the answer lies in [cur+1, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (P[mid + 1] >= t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ inline double cum_at(const double* P, const double* F, const double* w, int n, int& i,
+                                double t) {
+  if (t <= 0.0) return 0.0;
+  i = advance(P, n, i, t);
+  return i < n ? F[i] + (t - P[i]) * w[i] : F[n];
+}
+
+// LDS doubles per wave of the write pass: P, Q, Gq and the entry keys
+// (m + n - 1 at most)
+__host__ __device__ inline int write_lds_doubles(int m, int n) {
+  return (m + 1) + 2 * (n + 1) + (m + n + 1) / 2;
+}
+
+struct RecArgs {
+  int pair, G;     // bins per wave unit
+  int ng1, ng2;    // units per F1 slab (bins k), per F2 slab (bins j)
+  const PairGeo* geo;
+  const PairCtl* ctl;
+  const void* sb[3];
+  const double* ab;
+};
+
+// ---- pass 1: raw row marginals ------------------------------------------
+// Unit (j, g): bins (k, j), k in [g G, (g+1) G), of F1 slab j; lanes own
+// blocks of sources i.  rpart holds, per unit, the matched amount of each
+// source summed over its bins: its interval (P_i, P_{i+1}] clipped to
+// (0, QT], QT the bin's target total.
+template <typename T, int MAXB, bool UNI>
+__global__ __launch_bounds__(64 * kRecWaves) void k_rec_rows(RecArgs A, double* __restrict__ rpart) {
+  const int lane = threadIdx.x & 63;
+  const int u = blockIdx.x * kRecWaves + (threadIdx.x >> 6);
+  const PairGeo G = A.geo[A.pair];
+  const int m = G.m, n = G.n;
+  if (u >= n * A.ng1) return;
+  const int Bm = (m + 63) / 64, Bn = (n + 63) / 64;
+  const PairCtl c = A.ctl[A.pair];
+  const T* s = (const T*)A.sb[c.src];
+  const int j = u / A.ng1, g = u % A.ng1;
+  const int k0 = g * A.G, k1 = min(m, k0 + A.G);
+  double b1[MAXB];  // beta of F1 slab j (every bin of the unit)
+  preload<MAXB>(A.ab + G.f[0].aboff + (int64_t)j * 2 * m + m, m, Bm, lane, b1);
+  double acc[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) acc[b] = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    double va[MAXB], vb[MAXB], hi[MAXB], lo;
+    load_row<T, MAXB, UNI, true>(row_ref<T>(s, A.ab, G.f[0], j, k), m, Bm, c.sigma, b1, lane, va);
+    load_row<T, MAXB, UNI, false>(row_ref<T>(s, A.ab, G.f[1], k, j), n, Bn, c.sigma, nullptr, lane,
+                                  vb);
+    const double QT = block_totals<MAXB>(vb, n, Bn, lane, hi, lo);
+    (void)block_totals<MAXB>(va, m, Bm, lane, hi, lo);
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      acc[b] += fmax(0.0, fmin(hi[b], QT) - fmin(lo, QT));
+      lo = hi[b];
+    }
+  }
+  double* o = rpart + (int64_t)u * m;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int i = lane * Bm + b;
+    if (b < Bm && i < m) o[i] = acc[b];
+  }
+}
+
+// ---- pass 2: column marginals after the row scaling, raw column marginals,
+// entries per bin ---------------------------------------------------------
+// Unit (k, g): bins (k, j), j in [g G, (g+1) G), of F2 slab k; lanes own
+// blocks of targets l.  The row-scaled amount target l receives is
+// F(Q_{l+1}) - F(Q_l), F the cumulative row-scaled source amount (sources'
+// totals, F and the row factors in the wave's LDS; one search per lane, then
+// a forward cursor).  The bin's entries are the distinct values of the source
+// and target totals in (0, min(PT, QT)]: each ends one positive overlap.
+template <typename T, int MAXB, bool UNI>
+__global__ __launch_bounds__(64 * kRecWaves) void k_rec_cols(RecArgs A,
+                                                             const double* __restrict__ rho_r,
+                                                             double* __restrict__ cpart,
+                                                             double* __restrict__ c0part,
+                                                             long long* __restrict__ counts) {
   extern __shared__ double lds[];
-  const int item = blockIdx.x;
-  const int k = item / n, j = item % n;
-  const int lane = threadIdx.x;
-  const int64_t N1 = (int64_t)m * m * n;
-  const double* a = w + (int64_t)j * m * m + (int64_t)k * m;       // f1_{., k, j}
-  const double* b = w + N1 + (int64_t)k * n * n + (int64_t)j * n;  // f2_{k, j, .}
-  double* P = lds;
-  double* Q = lds + (m + 1);
-  stage_prefix(a, m, P, lane);
-  stage_prefix(b, n, Q, lane);
-  // scale factors of this bin's sources and targets (small, L2-resident)
-  const double* R = PASS != PASS_COUNT ? rho_r + (int64_t)j * m : nullptr;
-  const double* C = PASS >= PASS_BOTHSCALED ? rho_c + (int64_t)k * n : nullptr;
-  const double PT = P[m], QT = Q[n];
-  double* m1 = mt + (int64_t)j * m * m + (int64_t)k * m;
-  double* m2 = mt + N1 + (int64_t)k * n * n + (int64_t)j * n;
-  if (PASS == PASS_COUNT) {
-    // matched amount of source i: its interval clipped to (0, QT]; of target
-    // l likewise clipped to (0, PT]
-    for (int i = lane; i < m; i += 64) m1[i] = fmax(0.0, fmin(P[i + 1], QT) - fmin(P[i], QT));
-    for (int l = lane; l < n; l += 64) m2[l] = fmax(0.0, fmin(Q[l + 1], PT) - fmin(Q[l], PT));
-    long long cnt = 0;
-    double prev = 0.0;
-    for (int t0 = 0; t0 < m + n; t0 += 64) {
-      const Seg sg = bin_segment(P, Q, m, n, t0 + lane, lane, prev);
-      cnt += __popcll(__ballot(sg.ok));
+  const int lane = threadIdx.x & 63;
+  const int u = blockIdx.x * kRecWaves + (threadIdx.x >> 6);
+  const PairGeo G = A.geo[A.pair];
+  const int m = G.m, n = G.n;
+  if (u >= m * A.ng2) return;
+  const int Bm = (m + 63) / 64, Bn = (n + 63) / 64;
+  double* P = lds + (threadIdx.x >> 6) * 3 * (m + 1);
+  double* Fp = P + (m + 1);
+  double* W = Fp + (m + 1);
+  const PairCtl c = A.ctl[A.pair];
+  const T* s = (const T*)A.sb[c.src];
+  const int k = u / A.ng2, g = u % A.ng2;
+  const int j0 = g * A.G, j1 = min(n, j0 + A.G);
+  double b2[MAXB];  // beta of F2 slab k (every bin of the unit)
+  preload<MAXB>(A.ab + G.f[1].aboff + (int64_t)k * 2 * n + n, n, Bn, lane, b2);
+  double accc[MAXB], acc0[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) accc[b] = acc0[b] = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    double va[MAXB], vb[MAXB], hi[MAXB], lo;
+    load_row<T, MAXB, UNI, false>(row_ref<T>(s, A.ab, G.f[0], j, k), m, Bm, c.sigma, nullptr,
+                                  lane, va);
+    load_row<T, MAXB, UNI, true>(row_ref<T>(s, A.ab, G.f[1], k, j), n, Bn, c.sigma, b2, lane, vb);
+    double R[MAXB];  // row factors of the lane's sources (i, j)
+    preload<MAXB>(rho_r + (int64_t)j * m, m, Bm, lane, R);
+    // sources: totals, F at them, and the factors, into LDS
+    const double PT = block_totals<MAXB>(va, m, Bm, lane, hi, lo);
+    stage<MAXB>(hi, m, Bm, P, lane);
+    double w[MAXB], fsum[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) w[b] = va[b] * R[b];
+    block_sums<MAXB>(w, fsum);
+    stage<MAXB>(fsum, m, Bm, Fp, lane);
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int i = lane * Bm + b;
+      if (b < Bm && i < m) W[i] = R[b];
     }
-    if (lane == 0) counts[item] = cnt;
-  } else if (PASS == PASS_COLSCALED) {
-    // target-centric: sum_i pi_{i,l} rho_r(i,j)
-    for (int l = lane; l < n; l += 64) {
-      const double lo = Q[l], hi = Q[l + 1];
-      double acc = 0.0;
-      if (hi > lo) {
-        const int i_end = count_below(P, m, hi);  // the overlaps form one run of sources
-#pragma unroll 4
-        for (int i = first_above(P, m, lo); i < i_end; ++i) {
-          const double ov = fmin(P[i + 1], hi) - fmax(P[i], lo);
-          if (ov > 0.0) acc += ov * R[i];
+    // targets
+    double qlo;
+    double qhi[MAXB];
+    const double QT = block_totals<MAXB>(vb, n, Bn, lane, qhi, qlo);
+    const double T0 = fmin(PT, QT);
+    // entries: the distinct source totals in (0, T0] ...
+    int cnt = 0;
+    {
+      double pl = lo;
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) {
+        const int i = lane * Bm + b;
+        if (b < Bm && i < m && hi[b] > pl && hi[b] <= T0) ++cnt;
+        pl = hi[b];
+      }
+    }
+    wave_lds_sync();
+    int cur = first_at_least(P, m, fmin(qlo, PT));
+    double flo = cum_at(P, Fp, W, m, cur, fmin(qlo, PT));
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+      const int l = lane * Bn + b;
+      if (b < Bn && l < n) {
+        const double h = qhi[b];
+        acc0[b] += fmax(0.0, fmin(h, PT) - fmin(qlo, PT));
+        const double fhi = cum_at(P, Fp, W, m, cur, fmin(h, PT));
+        accc[b] += fhi - flo;
+        if (h > qlo && h <= T0) {
+          ++cnt;  // ... and target totals, a value that is both counted once
+          if (cur < m && P[cur + 1] == h) --cnt;
         }
+        flo = fhi;
+        qlo = h;
       }
-      m2[l] = acc;
     }
-  } else if (PASS == PASS_BOTHSCALED) {
-    for (int i = lane; i < m; i += 64) {
-      const double lo = P[i], hi = P[i + 1];
-      double acc = 0.0;
-      if (hi > lo) {
-        const int l_end = count_below(Q, n, hi);  // the overlaps form one run of targets
-#pragma unroll 4
-        for (int l = first_above(Q, n, lo); l < l_end; ++l) {
-          const double ov = fmin(hi, Q[l + 1]) - fmax(lo, Q[l]);
-          if (ov > 0.0) acc += ov * R[i] * C[l];
-        }
-      }
-      m1[i] = acc;
-    }
-    for (int l = lane; l < n; l += 64) {
-      const double lo = Q[l], hi = Q[l + 1];
-      double acc = 0.0;
-      if (hi > lo) {
-        const int i_end = count_below(P, m, hi);  // the overlaps form one run of sources
-#pragma unroll 4
-        for (int i = first_above(P, m, lo); i < i_end; ++i) {
-          const double ov = fmin(P[i + 1], hi) - fmax(P[i], lo);
-          if (ov > 0.0) acc += ov * R[i] * C[l];
-        }
-      }
-      m2[l] = acc;
-    }
-  } else {  // PASS_WRITE: the entries in order, 64 candidates per step
-    long long base = offsets[item];
-    double prev = 0.0;
-    for (int t0 = 0; t0 < m + n; t0 += 64) {
-      const Seg sg = bin_segment(P, Q, m, n, t0 + lane, lane, prev);
-      const unsigned long long mask = __ballot(sg.ok);
-      if (sg.ok) {
-        const long long pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-        osrc[pos] = sg.i * n + j;
-        odst[pos] = k * n + sg.l;
-        omass[pos] = (sg.hi - sg.lo) * R[sg.i] * C[sg.l];
-      }
-      base += __popcll(mask);
+    const int tot = wave_incl_sum_i(cnt);
+    if (lane == 63) counts[(int64_t)k * n + j] = tot;
+    wave_lds_sync();  // every lane is done with P, Fp, W before the next bin
+  }
+  double* o = cpart + (int64_t)u * n;
+  double* o0 = c0part + (int64_t)u * n;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int l = lane * Bn + b;
+    if (b < Bn && l < n) {
+      o[l] = accc[b];
+      o0[l] = acc0[b];
     }
   }
 }
 
-// Column sums of every slab of an unpadded slab-layout buffer:
-// out[0 .. n*m): F1 slab j column i at j*m + i; out[n*m ..): F2 slab k column l.
-__global__ __launch_bounds__(256) void k_slab_colsum(int m, int n, const double* __restrict__ mt,
-                                                     double* __restrict__ out) {
-  const int slab = blockIdx.x;  // 0..n-1: F1 slabs; n..n+m-1: F2 slabs
-  const int64_t M = (int64_t)m * n, N1 = (int64_t)m * m * n;
-  const bool f1 = slab < n;
-  const int L = f1 ? m : n;
-  const double* base = f1 ? mt + (int64_t)slab * m * m : mt + N1 + (int64_t)(slab - n) * n * n;
-  double* o = f1 ? out + (int64_t)slab * m : out + M + (int64_t)(slab - n) * n;
-  for (int q = threadIdx.x; q < L; q += 256) {
-    double acc = 0.0;
-    for (int p = 0; p < L; ++p) acc += base[(int64_t)p * L + q];
-    o[q] = acc;
+// ---- pass 3: the entries, and row marginals after both scalings ----------
+// Unit (j, g) as in pass 1.  Entries: the positive segments between
+// consecutive values of the merged source and target totals, in order; lane
+// t walks the merged positions [t S, (t+1) S) from a merge-path split (the
+// same work on every lane however the mass is spread), once to count and
+// once to write after a wave scan of the counts, so the bin's entries are
+// one contiguous run in walk order.  Row sums: per source, G(P_{i+1}) -
+// G(P_i) with G the cumulative column-scaled target amount, times R_i.
+template <typename T, int MAXB, bool UNI>
+__global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
+    RecArgs A, const double* __restrict__ rho_r, const double* __restrict__ rho_c,
+    const long long* __restrict__ offsets, double* __restrict__ r2part, int32_t* __restrict__ osrc,
+    int32_t* __restrict__ odst, double* __restrict__ omass) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int u = blockIdx.x * kRecWaves + (threadIdx.x >> 6);
+  const PairGeo G = A.geo[A.pair];
+  const int m = G.m, n = G.n;
+  if (u >= n * A.ng1) return;
+  const int Bm = (m + 63) / 64, Bn = (n + 63) / 64;
+  double* P = lds + (threadIdx.x >> 6) * write_lds_doubles(m, n);
+  double* Q = P + (m + 1);
+  double* Gq = Q + (n + 1);
+  unsigned* K = (unsigned*)(Gq + (n + 1));  // the bin's entries, (i << 16) | l
+  const PairCtl c = A.ctl[A.pair];
+  const T* s = (const T*)A.sb[c.src];
+  const int j = u / A.ng1, g = u % A.ng1;
+  const int k0 = g * A.G, k1 = min(m, k0 + A.G);
+  const double* Rg = rho_r + (int64_t)j * m;  // row factors of sources (i, j)
+  double b1[MAXB];  // beta of F1 slab j (every bin of the unit)
+  preload<MAXB>(A.ab + G.f[0].aboff + (int64_t)j * 2 * m + m, m, Bm, lane, b1);
+  const int S = (m + n + 63) / 64;  // merged positions per lane
+  double acc[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) acc[b] = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    double va[MAXB], vb[MAXB], ph[MAXB], qh[MAXB], plo, qlo;
+    load_row<T, MAXB, UNI, true>(row_ref<T>(s, A.ab, G.f[0], j, k), m, Bm, c.sigma, b1, lane, va);
+    load_row<T, MAXB, UNI, false>(row_ref<T>(s, A.ab, G.f[1], k, j), n, Bn, c.sigma, nullptr, lane,
+                                  vb);
+    const double* C = rho_c + (int64_t)k * n;  // column factors of targets (k, l)
+    (void)block_totals<MAXB>(va, m, Bm, lane, ph, plo);
+    stage<MAXB>(ph, m, Bm, P, lane);
+    const double QT = block_totals<MAXB>(vb, n, Bn, lane, qh, qlo);
+    stage<MAXB>(qh, n, Bn, Q, lane);
+    {  // G at the target totals: running sums of b_l C_l
+      double cw[MAXB], gs[MAXB];
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) {
+        const int l = lane * Bn + b;
+        cw[b] = (b < Bn && l < n) ? vb[b] * C[l] : 0.0;
+      }
+      block_sums<MAXB>(cw, gs);
+      stage<MAXB>(gs, n, Bn, Gq, lane);
+    }
+    wave_lds_sync();
+    // row sums after both scalings, per source of the lane's block
+    // (all cursor positions first, from LDS only; then every factor load at
+    // once, so the global latency is paid once per bin, not per source)
+    {
+      const double t0 = fmin(plo, QT);
+      int c0 = first_at_least(Q, n, t0);
+      if (t0 > 0.0) c0 = advance(Q, n, c0, t0);
+      int cb[MAXB];
+      int cur = c0;
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) {
+        const double t = fmin(ph[b], QT);
+        if (t > 0.0) cur = advance(Q, n, cur, t);
+        cb[b] = cur;
+      }
+      const double w0 = (t0 > 0.0 && c0 < n) ? C[c0] : 0.0;
+      double wb[MAXB];
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) wb[b] = cb[b] < n ? C[cb[b]] : 0.0;
+      double glo = t0 <= 0.0 ? 0.0 : (c0 < n ? Gq[c0] + (t0 - Q[c0]) * w0 : Gq[n]);
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) {
+        const int i = lane * Bm + b;
+        if (b < Bm && i < m) {
+          const double t = fmin(ph[b], QT);
+          const double ghi =
+              t <= 0.0 ? 0.0 : (cb[b] < n ? Gq[cb[b]] + (t - Q[cb[b]]) * wb[b] : Gq[n]);
+          acc[b] += ghi - glo;
+          glo = ghi;
+        }
+      }
+    }
+    // the merged walk: split at kb = lane S (how many of the first kb merged
+    // totals are source totals; ties: source first)
+    const int kb = min(m + n, lane * S), ke = min(m + n, kb + S);
+    int a, bq;
+    {
+      int lo = max(0, kb - n), hi = min(kb, m);
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid + 1] <= Q[kb - mid]) lo = mid + 1; else hi = mid;
+      }
+      a = lo;
+      bq = kb - lo;
+    }
+    const double u0 = fmax(P[a], Q[bq]);
+    int cnt = 0;
+    {
+      int aa = a, bb = bq;
+      double uu = u0;
+      for (int t = kb; t < ke; ++t) {
+        const bool takeP = aa < m && (bb >= n || P[aa + 1] <= Q[bb + 1]);
+        const double e = takeP ? P[aa + 1] : Q[bb + 1];
+        if (e > uu && aa < m && bb < n) ++cnt;
+        uu = e;
+        if (takeP) ++aa; else ++bb;
+      }
+    }
+    const int incl = wave_incl_sum_i(cnt);
+    const int total = readlane_i(incl, 63);
+    {  // the bin's (source, target) pairs into LDS, in walk order
+      int pos = incl - cnt;
+      int aa = a, bb = bq;
+      double uu = u0;
+      for (int t = kb; t < ke; ++t) {
+        const bool takeP = aa < m && (bb >= n || P[aa + 1] <= Q[bb + 1]);
+        const double e = takeP ? P[aa + 1] : Q[bb + 1];
+        if (e > uu && aa < m && bb < n) K[pos++] = ((unsigned)aa << 16) | (unsigned)bb;
+        uu = e;
+        if (takeP) ++aa; else ++bb;
+      }
+    }
+    wave_lds_sync();
+    // written out with consecutive lanes on consecutive entries; the mass is
+    // the overlap min(P_{i+1}, Q_{l+1}) - max(P_i, Q_l), the segment the walk
+    // found, times both factors
+    // (eight entries per lane at a time: their keys, then all their factor
+    // loads, then the stores)
+    const long long base = offsets[(int64_t)k * n + j];
+    for (int e0 = 0; e0 < total; e0 += 8 * 64) {
+      unsigned key[8];
+      double rf[8], cf[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + 64 * q + lane;
+        key[q] = e < total ? K[e] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        rf[q] = Rg[key[q] >> 16];
+        cf[q] = C[key[q] & 0xffffu];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + 64 * q + lane;
+        if (e < total) {
+          const int ia = (int)(key[q] >> 16), lb = (int)(key[q] & 0xffffu);
+          const double ov = fmin(P[ia + 1], Q[lb + 1]) - fmax(P[ia], Q[lb]);
+          osrc[base + e] = ia * n + j;
+          odst[base + e] = k * n + lb;
+          omass[base + e] = ov * rf[q] * cf[q];
+        }
+      }
+    }
+    wave_lds_sync();  // every lane is done with P, Q, Gq, K before the next bin
   }
+  double* o = r2part + (int64_t)u * m;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int i = lane * Bm + b;
+    if (b < Bm && i < m) o[i] = acc[b] * Rg[i];
+  }
+}
+
+// out[s*L + q] = sum_g part[(s*ng + g)*L + q], g ascending (fixed order)
+__global__ void k_part_reduce(const double* __restrict__ part, int nslab, int ng, int L,
+                              double* __restrict__ out) {
+  const int64_t tot = (int64_t)nslab * L;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = e / L, q = e % L;
+    const double* p = part + sl * ng * L + q;
+    double a = 0.0;
+    for (int g = 0; g < ng; ++g) a += p[(int64_t)g * L];
+    out[e] = a;
+  }
+}
+
+// c'' = rho_c c' (the column sums of the plan after both scalings)
+__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ b, int64_t M,
+                      double* __restrict__ out) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < M;
+       q += (int64_t)gridDim.x * blockDim.x)
+    out[q] = a[q] * b[q];
 }
 
 // rho = mu / sum where sum > mu, else 1 (out[q] for q in [0, M)); err[q] = |sum - mu|.
@@ -322,39 +659,50 @@ __global__ void k_deficits(int m, int n, const double* __restrict__ r2, const do
   }
 }
 
-// North-west-corner coupling of the deficits: er / ec with running totals
-// Er / Ec (M+1 entries each).
+// North-west-corner coupling of the deficits, as a merge of their running
+// totals Er, Ec (M+1 entries each, nondecreasing): the entries are the
+// positive segments between consecutive values of the merged breakpoints
+// {Er[1..M]} and {Ec[1..M]}; the segment ending at the idx-th smallest lies in
+// row s = #Er among the first idx and column t likewise.  Thread q walks the
+// merged positions [q S, (q+1) S) from a merge-path split, so the work is
+// balanced however the deficits are spread; it counts its entries, or
+// writes them from its offset (merged order = row, then column order).
 template <bool WRITE>
 __global__ void k_nw(int64_t M, const double* __restrict__ Er, const double* __restrict__ Ec,
                      long long* __restrict__ counts, const long long* __restrict__ offsets,
                      int32_t* __restrict__ osrc, int32_t* __restrict__ odst,
                      double* __restrict__ omass) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < M;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    const double lo = Er[s], hi = Er[s + 1];
+  const int64_t nthr = (2 * M + kNwSpan - 1) / kNwSpan;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nthr;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k0 = q * kNwSpan, k1 = (2 * M < k0 + kNwSpan) ? 2 * M : k0 + kNwSpan;
+    // a = how many of the first k0 merged breakpoints come from Er (ties: Er first)
+    int64_t lo = k0 > M ? k0 - M : 0, hi = k0 < M ? k0 : M;
+    while (lo < hi) {
+      const int64_t a = (lo + hi) >> 1;
+      if (Er[a + 1] <= Ec[k0 - a]) lo = a + 1; else hi = a;
+    }
+    int64_t a = lo, b = k0 - lo;
+    double u = fmax(Er[a], Ec[b]);
     long long cnt = 0;
-    long long pos = WRITE ? offsets[s] : 0;
-    if (hi > lo) {
-      int64_t a = 0, b = M;  // first t with Ec[t+1] > lo
-      while (a < b) {
-        const int64_t mid = (a + b) >> 1;
-        if (Ec[mid + 1] > lo) b = mid; else a = mid + 1;
-      }
-      for (int64_t t = a; t < M && Ec[t] < hi; ++t) {
-        const double ov = fmin(hi, Ec[t + 1]) - fmax(lo, Ec[t]);
-        if (ov > 0.0) {
-          if (WRITE) {
-            osrc[pos] = (int32_t)s;
-            odst[pos] = (int32_t)t;
-            omass[pos] = ov;
-            ++pos;
-          } else {
-            ++cnt;
-          }
+    long long pos = WRITE ? offsets[q] : 0;
+    for (int64_t k = k0; k < k1; ++k) {
+      const bool takeR = a < M && (b >= M || Er[a + 1] <= Ec[b + 1]);
+      const double e = takeR ? Er[a + 1] : Ec[b + 1];
+      if (e > u && a < M && b < M) {
+        if (WRITE) {
+          osrc[pos] = (int32_t)a;
+          odst[pos] = (int32_t)b;
+          omass[pos] = e - u;
+          ++pos;
+        } else {
+          ++cnt;
         }
       }
+      u = e;
+      if (takeR) ++a; else ++b;
     }
-    if (!WRITE) counts[s] = cnt;
+    if (!WRITE) counts[q] = cnt;
   }
 }
 
@@ -471,6 +819,18 @@ void sum_into(const double* in, int64_t n, double* part, double* out, hipStream_
 // Carves the recovery buffers out of the context's scratch (256-byte
 // aligned), growing it when this recovery needs more.  The caller holds
 // ctx->rec_mu.
+// the family's positions are 0, 1, .., L-1 (the grid of a problem without
+// explicit positions): the passes may then use p - q for X_p - X_q, exactly
+bool uniform_grid(const Workspace& ws, const PairGeo& g) {
+  for (int fam = 0; fam < 2; ++fam) {
+    const FamGeo& F = g.f[fam];
+    const double* X = &ws.tab_host[F.xoff - ws.lay.tab_off];
+    for (int q = 0; q < F.L; ++q)
+      if (X[q] != (double)q) return false;
+  }
+  return true;
+}
+
 struct ScratchCarver {
   hot_ctx* ctx;
   std::vector<std::pair<void**, size_t>> want;
@@ -507,6 +867,58 @@ struct ScratchCarver {
 
 using namespace hot;
 
+namespace hot {
+namespace {
+
+template <int MAXR, bool UNI>
+void launch_rec_passes(int pass, const RecArgs& A, bool fp32, int m, int n, const double* rho_r,
+                       const double* rho_c, double* part, double* part0, long long* counts,
+                       const long long* offs, int32_t* src, int32_t* dst, double* mass,
+                       hipStream_t st) {
+  const int64_t units = pass == 1 ? (int64_t)m * A.ng2 : (int64_t)n * A.ng1;
+  const dim3 grid((unsigned)((units + kRecWaves - 1) / kRecWaves)), block(64 * kRecWaves);
+  if (pass == 0) {
+    if (fp32) hipLaunchKernelGGL((k_rec_rows<float, MAXR, UNI>), grid, block, 0, st, A, part);
+    else hipLaunchKernelGGL((k_rec_rows<double, MAXR, UNI>), grid, block, 0, st, A, part);
+  } else if (pass == 1) {
+    const size_t lds = (size_t)kRecWaves * 3 * (m + 1) * sizeof(double);  // P, Fp, W
+    if (fp32)
+      hipLaunchKernelGGL((k_rec_cols<float, MAXR, UNI>), grid, block, lds, st, A, rho_r, part,
+                         part0, counts);
+    else
+      hipLaunchKernelGGL((k_rec_cols<double, MAXR, UNI>), grid, block, lds, st, A, rho_r, part,
+                         part0, counts);
+  } else {
+    const size_t lds = (size_t)kRecWaves * write_lds_doubles(m, n) * sizeof(double);
+    if (fp32)
+      hipLaunchKernelGGL((k_rec_write<float, MAXR, UNI>), grid, block, lds, st, A, rho_r, rho_c,
+                         offs, part, src, dst, mass);
+    else
+      hipLaunchKernelGGL((k_rec_write<double, MAXR, UNI>), grid, block, lds, st, A, rho_r, rho_c,
+                         offs, part, src, dst, mass);
+  }
+}
+
+void rec_pass(int pass, const RecArgs& A, bool fp32, bool uni, int m, int n, const double* rho_r,
+              const double* rho_c, double* part, double* part0, long long* counts,
+              const long long* offs, int32_t* src, int32_t* dst, double* mass, hipStream_t st) {
+  const int rounds = (std::max(m, n) + 63) / 64;
+#define HOT_REC(R)                                                                           \
+  (uni ? launch_rec_passes<R, true>(pass, A, fp32, m, n, rho_r, rho_c, part, part0, counts,  \
+                                    offs, src, dst, mass, st)                                \
+       : launch_rec_passes<R, false>(pass, A, fp32, m, n, rho_r, rho_c, part, part0, counts, \
+                                     offs, src, dst, mass, st))
+  if (rounds <= 1) HOT_REC(1);
+  else if (rounds <= 2) HOT_REC(2);
+  else if (rounds <= 4) HOT_REC(4);
+  else if (rounds <= 8) HOT_REC(8);
+  else HOT_REC(16);
+#undef HOT_REC
+}
+
+}  // namespace
+}  // namespace hot
+
 extern "C" hot_status hot_recover_plan(hot_ctx* ctx, const hot_solution* sol, hot_stream_t stream,
                                        int32_t* src, int32_t* dst, double* mass,
                                        int64_t capacity, int64_t* nnz, double* marg_err) {
@@ -515,7 +927,6 @@ extern "C" hot_status hot_recover_plan(hot_ctx* ctx, const hot_solution* sol, ho
   ctx->err.clear();
   const int m = sol->m, n = sol->n;
   const int64_t M = (int64_t)m * n;
-  const int64_t N1 = (int64_t)m * m * n, N = N1 + (int64_t)m * n * n;
   if (capacity < hot_plan_capacity(m, n)) {
     ctx->err = "plan capacity below hot_plan_capacity(m, n)";
     return HOT_E_INVALID;
@@ -526,85 +937,86 @@ extern "C" hot_status hot_recover_plan(hot_ctx* ctx, const hot_solution* sol, ho
   const double* mu2 = ws.arr + arr_mu2(g);
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> rec_lock(ctx->rec_mu);  // the scratch is the context's
-  double *w, *mt, *sums, *sums2, *rho_r, *rho_c, *err, *er, *ec, *Er, *Ec, *fb, *part, *res;
+  // bin units: G consecutive bins of one slab per wave, about 8192 waves in all
+  RecArgs A;
+  A.pair = sol->pair;
+  A.G = (int)std::max<int64_t>(1, (M + 8191) / 8192);
+  A.ng1 = (m + A.G - 1) / A.G;
+  A.ng2 = (n + A.G - 1) / A.G;
+  A.geo = ws.args.geo;
+  A.ctl = ws.args.ctl[0];
+  for (int b = 0; b < 3; ++b) A.sb[b] = ws.args.sb[b];
+  A.ab = ws.args.ab;
+  const int64_t npart = std::max((int64_t)n * A.ng1 * m, (int64_t)m * A.ng2 * n);
+  const int64_t nthr_nw = (2 * M + kNwSpan - 1) / kNwSpan;
+  double *part, *part0, *r, *c0, *c1, *c2, *r2, *rho_r, *rho_c, *err, *er, *ec, *Er, *Ec, *fb,
+      *sp, *res;
   long long *counts, *offs, *ncounts, *noffs, *ibsum;
-  const int64_t nbs = (std::max(N, M) + kScanBlock - 1) / kScanBlock + 2;
+  const int64_t nbs = (std::max(M, nthr_nw) + kScanBlock - 1) / kScanBlock + 2;
   ScratchCarver B{ctx, {}};
-  B.add(&w, N); B.add(&mt, N); B.add(&sums, 2 * M); B.add(&sums2, 2 * M);
+  B.add(&part, npart); B.add(&part0, npart);
+  B.add(&r, M); B.add(&c0, M); B.add(&c1, M); B.add(&c2, M); B.add(&r2, M);
   B.add(&rho_r, M); B.add(&rho_c, M); B.add(&err, M); B.add(&er, M); B.add(&ec, M);
-  B.add(&Er, M + 1); B.add(&Ec, M + 1); B.add(&fb, nbs); B.add(&part, nbs); B.add(&res, 8);
-  B.add(&counts, M); B.add(&offs, M + 1); B.add(&ncounts, M); B.add(&noffs, M + 1);
+  B.add(&Er, M + 1); B.add(&Ec, M + 1); B.add(&fb, nbs); B.add(&sp, nbs); B.add(&res, 8);
+  B.add(&counts, M); B.add(&offs, M + 1); B.add(&ncounts, nthr_nw); B.add(&noffs, nthr_nw + 1);
   B.add(&ibsum, nbs);
   if (!B.commit()) {
     ctx->err = "recovery workspace allocation failed";
     return HOT_E_NOMEM;
   }
-  const LaunchArgs& a = ws.args;
-  const int pair = sol->pair;
-  if (a.fp32)
-    hipLaunchKernelGGL(k_clip_flows<float>, dim3(grid_for(N)), dim3(256), 0, st, a.geo, a.ctl[0],
-                       pair, (const float*)a.sb[0], (const float*)a.sb[1], (const float*)a.sb[2],
-                       a.ab, w);
-  else
-    hipLaunchKernelGGL(k_clip_flows<double>, dim3(grid_for(N)), dim3(256), 0, st, a.geo,
-                       a.ctl[0], pair, (const double*)a.sb[0], (const double*)a.sb[1],
-                       (const double*)a.sb[2], a.ab, w);
-  const size_t lds = (size_t)(m + n + 2) * sizeof(double);  // P, Q
-  // pass A: counts and matched amounts -> raw marginals r (layout [j][i]), c ([k][l])
-  hipLaunchKernelGGL(k_rec_bin<PASS_COUNT>, dim3((unsigned)M), dim3(64), lds, st, m, n, w, mt,
-                     counts, (const long long*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-                     (double*)nullptr);
-  hipLaunchKernelGGL(k_slab_colsum, dim3(n + m), dim3(256), 0, st, m, n, mt, sums);
-  // raw errors and row scale factors
-  hipLaunchKernelGGL(k_scale_down, dim3(grid_for(M)), dim3(256), 0, st, sums, mu1T, M, rho_r, err);
-  sum_into(err, M, part, res + 0, st);
-  // pass B: column sums after the row scaling
-  hipLaunchKernelGGL(k_rec_bin<PASS_COLSCALED>, dim3((unsigned)M), dim3(64), lds, st, m, n, w, mt,
-                     counts, (const long long*)nullptr, rho_r, (const double*)nullptr,
-                     (int32_t*)nullptr, (int32_t*)nullptr, (double*)nullptr);
-  hipLaunchKernelGGL(k_slab_colsum, dim3(n + m), dim3(256), 0, st, m, n, mt, sums2);
-  hipLaunchKernelGGL(k_scale_down, dim3(grid_for(M)), dim3(256), 0, st, sums2 + M, mu2, M, rho_c,
-                     err);
-  // raw column error uses the unscaled column sums
-  hipLaunchKernelGGL(k_scale_down, dim3(grid_for(M)), dim3(256), 0, st, sums + M, mu2, M, er, err);
-  sum_into(err, M, part, res + 1, st);
-  // pass C: row and column sums after both scalings
-  hipLaunchKernelGGL(k_rec_bin<PASS_BOTHSCALED>, dim3((unsigned)M), dim3(64), lds, st, m, n, w,
-                     mt, counts, (const long long*)nullptr, rho_r, rho_c, (int32_t*)nullptr,
-                     (int32_t*)nullptr, (double*)nullptr);
-  hipLaunchKernelGGL(k_slab_colsum, dim3(n + m), dim3(256), 0, st, m, n, mt, sums2);
-  hipLaunchKernelGGL(k_deficits, dim3(grid_for(M)), dim3(256), 0, st, m, n, sums2, sums2 + M,
-                     mu1T, mu2, er, ec);
-  scan<double>(er, M, Er, fb, st);
-  scan<double>(ec, M, Ec, fb, st);
-  // offsets of the bin entries and of the coupling entries
+  const bool fp32 = ws.args.fp32 != 0;
+  // uniform grid: no positions given (the cost table holds X_p = p)
+  const bool uni = ws.tab_host.empty() ? false : uniform_grid(ws, g);
+  // pass 1: raw row marginals r ([j][i]) -> row factors, raw row error
+  rec_pass(0, A, fp32, uni, m, n, nullptr, nullptr, part, nullptr, nullptr, nullptr, nullptr, nullptr,
+           nullptr, st);
+  hipLaunchKernelGGL(k_part_reduce, dim3(grid_for(M)), dim3(256), 0, st, part, n, A.ng1, m, r);
+  hipLaunchKernelGGL(k_scale_down, dim3(grid_for(M)), dim3(256), 0, st, r, mu1T, M, rho_r, err);
+  sum_into(err, M, sp, res + 0, st);
+  // pass 2: column marginals after the row scaling c1 and raw c0 ([k][l]),
+  // entries per bin -> column factors, raw column error
+  rec_pass(1, A, fp32, uni, m, n, rho_r, nullptr, part, part0, counts, nullptr, nullptr, nullptr,
+           nullptr, st);
+  hipLaunchKernelGGL(k_part_reduce, dim3(grid_for(M)), dim3(256), 0, st, part, m, A.ng2, n, c1);
+  hipLaunchKernelGGL(k_part_reduce, dim3(grid_for(M)), dim3(256), 0, st, part0, m, A.ng2, n, c0);
+  hipLaunchKernelGGL(k_scale_down, dim3(grid_for(M)), dim3(256), 0, st, c1, mu2, M, rho_c, err);
+  hipLaunchKernelGGL(k_scale_down, dim3(grid_for(M)), dim3(256), 0, st, c0, mu2, M, er, err);
+  sum_into(err, M, sp, res + 1, st);
   scan<long long>(counts, M, offs, ibsum, st);
-  hipLaunchKernelGGL(k_nw<false>, dim3(grid_for(M)), dim3(256), 0, st, M, Er, Ec, ncounts,
-                     (const long long*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-                     (double*)nullptr);
-  scan<long long>(ncounts, M, noffs, ibsum, st);
   long long tot[2] = {0, 0};
   if (hipMemcpyAsync(&tot[0], offs + M, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&tot[1], noffs + M, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     ctx->err = "recovery count copy failed";
     return HOT_E_DEVICE;
   }
-  if (tot[0] + tot[1] > capacity) {
+  // the repair adds at most 2M - 1 entries, so the Algorithm 1 part must
+  // leave that much room
+  if (tot[0] + 2 * M - 1 > capacity) {
     ctx->err = "plan entries exceed capacity";
     return HOT_E_INVALID;
   }
-  hipLaunchKernelGGL(k_rec_bin<PASS_WRITE>, dim3((unsigned)M), dim3(64), lds, st, m, n, w, mt,
-                     counts, offs, rho_r, rho_c, src, dst, mass);
-  hipLaunchKernelGGL(k_nw<true>, dim3(grid_for(M)), dim3(256), 0, st, M, Er, Ec, ncounts, noffs,
-                     src + tot[0], dst + tot[0], mass + tot[0]);
-  hipLaunchKernelGGL(k_final_err, dim3(grid_for(M)), dim3(256), 0, st, m, n, sums2, sums2 + M,
-                     mu1T, mu2, Er, Ec, er, ec);
-  sum_into(er, M, part, res + 2, st);
-  sum_into(ec, M, part, res + 3, st);
+  // pass 3: the entries, both scalings applied; row sums after both r2
+  rec_pass(2, A, fp32, uni, m, n, rho_r, rho_c, part, nullptr, nullptr, offs, src, dst, mass, st);
+  hipLaunchKernelGGL(k_part_reduce, dim3(grid_for(M)), dim3(256), 0, st, part, n, A.ng1, m, r2);
+  hipLaunchKernelGGL(k_mul, dim3(grid_for(M)), dim3(256), 0, st, rho_c, c1, M, c2);
+  // deficits, their north-west-corner coupling after the Algorithm 1 entries
+  hipLaunchKernelGGL(k_deficits, dim3(grid_for(M)), dim3(256), 0, st, m, n, r2, c2, mu1T, mu2, er,
+                     ec);
+  scan<double>(er, M, Er, fb, st);
+  scan<double>(ec, M, Ec, fb, st);
+  hipLaunchKernelGGL(k_nw<false>, dim3(grid_for(nthr_nw)), dim3(256), 0, st, M, Er, Ec, ncounts,
+                     (const long long*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                     (double*)nullptr);
+  scan<long long>(ncounts, nthr_nw, noffs, ibsum, st);
+  hipLaunchKernelGGL(k_nw<true>, dim3(grid_for(nthr_nw)), dim3(256), 0, st, M, Er, Ec, ncounts,
+                     noffs, src + tot[0], dst + tot[0], mass + tot[0]);
+  hipLaunchKernelGGL(k_final_err, dim3(grid_for(M)), dim3(256), 0, st, m, n, r2, c2, mu1T, mu2,
+                     Er, Ec, er, ec);
+  sum_into(er, M, sp, res + 2, st);
+  sum_into(ec, M, sp, res + 3, st);
   double errs[4];
   if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&tot[1], noffs + nthr_nw, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(errs, res, 4 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     ctx->err = "recovery kernels failed";
