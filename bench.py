@@ -138,8 +138,14 @@ def run_serving(args):
             if t > now:
                 time.sleep(t - now)
             a, b = pool[n][seed % args.pool]
-            prec = hot.HOT_FP32_STREAM if tol >= 1e-4 else hot.HOT_FP64
-            srv.submit(a, b, q, tol=tol, prec=prec, max_iter=1000000, flags=flags)
+            if tol >= 1e-4:
+                srv.submit(a, b, q, tol=tol, prec=hot.HOT_FP32_STREAM, max_iter=1000000,
+                           flags=flags)
+            elif args.fp32_first:  # FP32 streams until the KKT stalls, then FP64
+                srv.submit(a, b, q, tol=tol, prec=hot.HOT_FP32_STREAM, max_iter=1000000,
+                           flags=flags | hot.HOT_FLAG_ESCALATE)
+            else:
+                srv.submit(a, b, q, tol=tol, prec=hot.HOT_FP64, max_iter=1000000, flags=flags)
 
     th = threading.Thread(target=feeder)
     th.start()
@@ -174,7 +180,9 @@ def run_serving(args):
         "data": "synthetic",
         "config": {"workload": f"serving: Poisson {args.rate:g} req/s for {args.duration:g} s, "
                                "n~U{64,96,128,192,256}, 1-5 Gaussian blobs, tol 1e-4 (70%, FP32 "
-                               "streams) / 1e-6 (30%, FP64), continuous batching"
+                               "streams) / 1e-6 (30%, "
+                               + ("FP32 streams widened to FP64 on a stall" if args.fp32_first
+                                  else "FP64") + "), continuous batching"
                                + (", sigma re-balanced at restarts" if args.sigma_update else ""),
                    "requests": len(trace), "slots": args.slots},
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
@@ -183,7 +191,14 @@ def run_serving(args):
         "drain_cap_s": args.drain,
         "converged": int(sum(r["status"] == 0 for r in results)),
         "max_resident": st["max_resident"], "iters_mean": float(iters.mean()),
+        "escalated": int(sum(r["escalated_at"] > 0 for r in results)),
     }
+    tight = [r for r in results if trace[r["tag"]][2] < 1e-4]
+    if tight:
+        lt = np.array([r["latency"] for r in tight])
+        out["tight_tol"] = {"count": len(tight), "latency_p50_s": float(np.percentile(lt, 50)),
+                            "latency_p99_s": float(np.percentile(lt, 99)),
+                            "converged": int(sum(r["status"] == 0 for r in tight))}
     print(json.dumps(out), flush=True)
 
 
@@ -313,6 +328,11 @@ def main():
                     help="override the workload's relative KKT tolerance")
     ap.add_argument("--admm", action="store_true",
                     help="the generalized ADMM baseline (rho 1.7) instead of HOT")
+    ap.add_argument("--escalate", action="store_true",
+                    help="FP32 streams widened to FP64 when the KKT stalls (single pairs)")
+    ap.add_argument("--fp32-first", action="store_true",
+                    help="serving: 1e-6 requests start on FP32 streams and widen to FP64 "
+                         "on a stall")
     ap.add_argument("--abs-kkt", action="store_true",
                     help="stop on the absolute KKT residual ||R(w_bar)|| instead of the relative one")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -332,7 +352,7 @@ def main():
 
     pairs, tol, prec, base = make_workload(args.workload, args.pairs)
     default_run = (args.prec is None and args.tol is None and not args.sigma_update
-                   and not args.admm and not args.abs_kkt)
+                   and not args.admm and not args.abs_kkt and not args.escalate)
     if args.prec is not None:
         prec = hot.HOT_FP32_STREAM if args.prec == "fp32" else hot.HOT_FP64
     if args.tol is not None:
@@ -348,6 +368,9 @@ def main():
     if args.abs_kkt:
         flags |= hot.HOT_FLAG_ABS_KKT
         desc = desc.replace("rel KKT", "abs KKT")
+    if args.escalate:
+        flags |= hot.HOT_FLAG_ESCALATE
+        desc += ", widened to FP64 on a stall"
     if args.admm:
         desc += ", generalized ADMM (rho 1.7)"
     kw = dict(tol=tol, max_iter=1000000, prec=prec, flags=flags)
@@ -433,6 +456,7 @@ def main():
                         "kkt_abs_max": float(max(r["kkt_abs"] for r in results)),
                         "restarts_mean": float(np.mean([r["restarts"] for r in results])),
                         "feaserr_max": float(max(r["feaserr"] for r in results)),
+                        "escalated": int(sum(r["escalated_at"] > 0 for r in results)),
                         "converged": int(sum(r["status"] == 0 for r in results))},
     }
     if quality is not None:

@@ -73,6 +73,18 @@ typedef enum {
                                      sigma > 0).  Costs one more state-sized
                                      buffer and one more stream on check and
                                      restart passes. */
+#define HOT_FLAG_ESCALATE 0x20u   /* with HOT_FP32_STREAM: when the relative KKT
+                                     stops improving above tol (not halved
+                                     over the last max(1000, k_best / 4)
+                                     iterations, at least two restarts
+                                     done), widen the state to FP64 in place
+                                     (exactly), start a new epoch there (one
+                                     restart pass, counted in restarts and
+                                     iters) and continue with FP64 streams;
+                                     hot_result.escalated_at records the
+                                     iteration.  hot_solve and the server
+                                     act on it; batches and hot_solve_noalloc
+                                     ignore it. */
 
 typedef struct {
   int32_t m, n;            /* grid rows, columns: 1 <= m, n <= 1024 */
@@ -112,7 +124,8 @@ typedef struct {
   int32_t iters;      /* updates performed (Alg. 2 iterations) */
   int32_t restarts;
   int32_t status;     /* hot_status of this problem */
-  int32_t reserved;
+  int32_t escalated_at; /* HOT_FLAG_ESCALATE: iteration count at which the
+                           FP32 streams were widened to FP64, 0 if never */
   double feaserr;     /* max(||min(x_bar, 0)|| / (1 + ||x_bar||), res_primal): the
                          relative primal feasibility error of the experiments
                          (Sec. 4.1, the metric feaserr) */

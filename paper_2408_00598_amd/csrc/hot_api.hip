@@ -40,6 +40,7 @@ void launch_aat_solve(const LaunchArgs& a, int pair, int64_t M, const double* R,
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
                              double* out, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);
+void launch_widen(const void* in, void* out, int64_t n, hipStream_t st);
 void launch_finalize(const LaunchArgs& a, const SlabItem* items_all, int nitems_all, int npairs,
                      hipStream_t st);
 void* static_scratch_init(int device, std::string& err);
@@ -261,6 +262,7 @@ hot_status validate_problem_public(hot_ctx* ctx, const hot_problem* p) {
 // blocks, copy tables and clear the state.  Synchronises `st` once.
 hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st) {
   const size_t np = lay.geo.size();
+  escalated_at = 0;
   restore_tables();  // (no graph is in flight between runs)
   drop_retired();
   std::vector<const double*> ptrs(2 * np);
@@ -465,15 +467,90 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   return HOT_OK;
 }
 
+hot_status Workspace::escalate(hot_ctx* ctx, hipStream_t st) {
+  if (!lay.fp32 || arena) return HOT_OK;
+  const size_t bytes = (size_t)lay.state_elems * 8;
+  void* nb[3] = {nullptr, nullptr, nullptr};
+  void* nx = nullptr;
+  hot_status s = HOT_OK;
+  for (int b = 0; b < 3 && s == HOT_OK; ++b) s = device_buffer(ctx, &nb[b], bytes);
+  if (s == HOT_OK && sbx) s = device_buffer(ctx, &nx, bytes);
+  if (s != HOT_OK) return s;  // (the new buffers stay in allocs, freed with the workspace)
+  for (int b = 0; b < 3; ++b) launch_widen(sb[b], nb[b], lay.state_elems, st);
+  if (sbx) launch_widen(sbx, nx, lay.state_elems, st);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));
+  auto drop = [&](void* p) {
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) allocs.erase(it);
+    (void)hipFree(p);
+  };
+  for (int b = 0; b < 3; ++b) {
+    drop(sb[b]);
+    sb[b] = nb[b];
+    args.sb[b] = nb[b];
+  }
+  if (sbx) {
+    drop(sbx);
+    sbx = nx;
+    args.sbx = nx;
+  }
+  relane_layout(lay, 0, ctx->tune);
+  HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), lay.geo.size() * sizeof(PairGeo),
+                       hipMemcpyHostToDevice, st));
+  // A new epoch starts at the widened state: the next pass is a restart pass
+  // (anchor = max(s - g, g) with the y_bar already solved for s).  Without it
+  // the FP64 passes would continue an epoch whose Halpern weight has decayed
+  // over the stalled FP32 iterations and whose restart reference sits at the
+  // FP32 noise floor.  At a graph boundary the next pass reads ctl[0].
+  std::vector<PairCtl> c0(lay.geo.size());
+  HIPCK(hipMemcpyAsync(c0.data(), ctl_d, c0.size() * sizeof(PairCtl), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  for (PairCtl& c : c0) {
+    // (src == 2: an epoch starts at this very state already)
+    if (c.status != ST_RUNNING || c.mode == MODE_INIT || c.mode == MODE_IDLE || c.src == 2)
+      continue;
+    c.mode = MODE_RESTART;
+    c.sig_old = c.sigma;
+    c.k = 0;
+    c.it += 1;
+    c.restarts += 1;
+  }
+  HIPCK(hipMemcpyAsync(ctl_d, c0.data(), c0.size() * sizeof(PairCtl), hipMemcpyHostToDevice, st));
+  HIPCK(hipStreamSynchronize(st));
+  args.fp32 = 0;
+  args.maxvpl = lay.maxvpl;
+  args.unroll = ctx->tune.unroll_for(lay.key_elems, lay.key_pairs, 0);
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  graph_exec = nullptr;
+  graph = nullptr;
+  return HOT_OK;
+}
+
+// Stall of an FP32-stream solve (HOT_FLAG_ESCALATE): the relative KKT at the
+// checks has not halved over the last max(1000, k_best / 4) iterations, k_best
+// the iteration of the last halving, with at least two restarts done.  (A
+// restarted solve in FP64 halves its KKT every few hundred iterations on
+// these grids; a premature switch costs at most the FP64 price per pass.)
+bool StallWatch::stalled(const PairCtl& c) {
+  if (c.kkt > 0.0 && (best == 0.0 || c.kkt < 0.5 * best)) {
+    best = c.kkt;
+    it_best = c.it;
+  }
+  return best > 0.0 && c.restarts >= 2 &&
+         (int64_t)c.it - it_best > std::max<int64_t>(1000, it_best / 4);
+}
+
 static bool use_graphs() {
   const char* e = std::getenv("HOT_NO_GRAPH");
   return !(e && e[0] == '1');
 }
 
 // Run graph launches until every problem has stopped.
-hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
+hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs, StallWatch* watch) {
   const size_t np = lay.geo.size();
-  if (profile) return run_profiled(ctx, st, max_graphs);
+  if (profile) return run_profiled(ctx, st, max_graphs, watch);
   const bool graphs = use_graphs();
   if (graphs && !graph_exec) {
     HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -530,9 +607,34 @@ hot_status Workspace::run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
       }
       break;
     }
+    if (watch && lay.fp32 && np == 1 && watch->stalled(hc[cur][0])) {
+      // drain the graph in flight, widen the state, restart the pipeline
+      // (at a graph boundary the latest control blocks are ctl[0])
+      e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = hipMemcpy(hc[0], ctl_d, np * sizeof(PairCtl), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) break;
+      if (hc[0][0].status != ST_RUNNING) break;
+      const hot_status es = escalate(ctx, st);
+      if (es != HOT_OK) {
+        result = es;
+        break;
+      }
+      escalated_at = hc[0][0].it;
+      if (graphs) {
+        const hot_status gs = ensure_graph(ctx, st);
+        if (gs != HOT_OK) {
+          result = gs;
+          break;
+        }
+      }
+      e = launch_one(0);
+      ++launched;
+      cur = 0;
+      continue;
+    }
     cur ^= 1;
   }
-  if (e != hipSuccess) {
+  if (e != hipSuccess && result == HOT_OK) {
     ctx->err = std::string("iteration launch failed: ") + hipGetErrorString(e);
     result = HOT_E_DEVICE;
   }
@@ -598,11 +700,13 @@ hipError_t Workspace::finalize(hipStream_t st) {
 // Profiling run: direct launches, a hipEvent pair around every slab pass on
 // the workspace stream, no pipelining.  Same kernels and iteration order as
 // the graph path.
-hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs) {
+hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs,
+                                   StallWatch* watch) {
   const size_t np = lay.geo.size();
   std::vector<hipEvent_t> evs(2 * kGraphIters);
   for (auto& e : evs) HIPCK(hipEventCreate(&e));
   hot_status result = HOT_OK;
+  bool esc_next = false;  // widen one graph after the stall, as run() does
   for (int64_t g = 0; g < max_graphs; ++g) {
     for (int i = 0; i < kGraphIters; ++i) {
       HIPCK(hipEventRecord(evs[2 * i], st));
@@ -624,6 +728,14 @@ hot_status Workspace::run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_gra
     for (size_t p = 0; p < np; ++p)
       if (host_ctl[p].status == ST_RUNNING) all_done = false;
     if (all_done) break;
+    if (esc_next) {
+      esc_next = false;
+      result = escalate(ctx, st);
+      if (result != HOT_OK) break;
+      escalated_at = host_ctl[0].it;
+    } else if (watch && lay.fp32 && np == 1 && watch->stalled(host_ctl[0])) {
+      esc_next = true;
+    }
   }
   for (auto& e : evs) (void)hipEventDestroy(e);
   HIPCK(finalize(st));
@@ -774,6 +886,7 @@ void Workspace::fill_result(int p, hot_result* r, double seconds) const {
   r->restarts = c.restarts;
   r->status = (int32_t)status_of(c.status);
   r->feaserr = c.feaserr;
+  r->escalated_at = escalated_at;
 }
 
 }  // namespace hot
@@ -1103,7 +1216,10 @@ hot_status hot_solve(hot_ctx* ctx, const hot_problem* prob, hot_stream_t stream,
   s = ws->setup(ctx, prob, 1, st);
   if (s != HOT_OK) return s;
   const int64_t max_graphs = (int64_t)prob->max_iter * 2 / kGraphIters + 8;
-  s = ws->run(ctx, st, max_graphs);
+  StallWatch watch;
+  const bool esc = (prob->flags & HOT_FLAG_ESCALATE) && prob->prec == HOT_FP32_STREAM &&
+                   !(prob->flags & HOT_FLAG_FIXED_ITERS) && prob->tol > 0;
+  s = ws->run(ctx, st, max_graphs, esc ? &watch : nullptr);
   if (s != HOT_OK) return s;
   collect_profile(ctx, *ws);
   const double secs =

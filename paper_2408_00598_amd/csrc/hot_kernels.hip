@@ -913,6 +913,13 @@ __global__ void k_zero(uint4* __restrict__ p, int64_t n16, uint32_t* __restrict_
   for (int64_t q = t0; q < ntail; q += stride) tail[q] = 0u;
 }
 
+// FP32 state widened to FP64 (exact).
+__global__ void k_widen(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (double)in[e];
+}
+
 // mu1T[j][i] = mu1[i][j], mu2[k][l] copied.
 __global__ void k_setup_mu(const double* __restrict__ mu1, const double* __restrict__ mu2,
                            int m, int n, double* __restrict__ mu1T, double* __restrict__ mu2c) {
@@ -1134,6 +1141,11 @@ void launch_finalize(const LaunchArgs& a, const SlabItem* items_all, int nitems_
                        a.geo, a.ctl[0], (const double*)a.sb[0], (const double*)a.sb[1],
                        (const double*)a.sb[2], a.ab, a.kitem);
   hipLaunchKernelGGL(k_feas_pairs, dim3(npairs), dim3(kWG), 0, st, a.geo, a.ctl[0], a.kitem);
+}
+
+void launch_widen(const void* in, void* out, int64_t n, hipStream_t st) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kWG - 1) / kWG, 65536));
+  hipLaunchKernelGGL(k_widen, dim3(grid), dim3(kWG), 0, st, (const float*)in, (double*)out, n);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t st) {

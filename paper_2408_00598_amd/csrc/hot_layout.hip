@@ -82,7 +82,12 @@ size_t Layout::bytes(uint32_t flags) const {
   const size_t su = (flags & HOT_FLAG_SIGMA_UPDATE)
                         ? (size_t)state_elems * elem_size + (size_t)tab_off * 8 + 512
                         : 0;
-  return su + (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
+  // widening FP32 streams to FP64 allocates FP64 state buffers (3, and x_bar
+  // with sigma re-balancing) while the FP32 ones still exist
+  const size_t esc = (fp32 && (flags & HOT_FLAG_ESCALATE))
+                         ? (size_t)state_elems * 8 * ((flags & HOT_FLAG_SIGMA_UPDATE) ? 4 : 3)
+                         : 0;
+  return su + esc + (size_t)state_elems * elem_size * 3 + (size_t)ab_len * 8 + (size_t)rs_len * 8 * 2 +
          (size_t)cp_len * 8 * 2 + (size_t)items.size() * (kKI * 8 + sizeof(SlabItem)) +
          sitems.size() * sizeof(SmallItem) +
          (size_t)arr_len * 8 + (size_t)vec_len * 8 + geo.size() * sizeof(PairGeo) +
@@ -109,6 +114,8 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   // this total)
   const int npairs = key_pairs >= 0 ? key_pairs : (int)shapes.size();
   if (key_elems >= 0) total = key_elems;
+  lay.key_elems = total;
+  lay.key_pairs = npairs;
   const int64_t item_elems = tune.item_elems_for(total, npairs, fp32);
   int64_t soff = 0, aboff = 0, rsoff = 0, cpoff = 0, moff = 0, voff = 0, taboff = 0;
   int maxvpl = 1;
@@ -235,6 +242,28 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   lay.vec_len = std::max<int64_t>(voff, 1);
   lay.maxvpl = maxvpl;
   return true;
+}
+
+// Lanes of every family for streams of another precision on the same pitches,
+// offsets and row chunks: when a solve's FP32 state is widened to FP64 in
+// place, the elements per 16-byte vector change and the buffer geometry does
+// not (an FP32 pitch is a multiple of 4 elements, so also of 2).
+void relane_layout(Layout& lay, int fp32, const Tuning& tune) {
+  const int W = fp32 ? 4 : 2;
+  int maxvpl = 1;
+  for (PairGeo& g : lay.geo)
+    for (int fam = 0; fam < 2; ++fam) {
+      FamGeo& F = g.f[fam];
+      const int Q = F.P / W;
+      const int vt = tune.vec_per_lane_for(lay.key_elems, lay.key_pairs, fp32);
+      const int LR = std::min(64, next_pow2((Q + vt - 1) / vt));
+      F.lrs = ilog2(LR);
+      F.vpl = (Q + LR - 1) / LR;
+      maxvpl = std::max(maxvpl, F.vpl);
+    }
+  lay.fp32 = fp32;
+  lay.elem_size = fp32 ? 4 : 8;
+  lay.maxvpl = maxvpl;
 }
 
 }  // namespace hot

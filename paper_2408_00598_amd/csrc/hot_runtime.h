@@ -102,6 +102,8 @@ struct Layout {
   int64_t state_elems = 0, ab_len = 0, rs_len = 0, cp_len = 0, arr_len = 0, vec_len = 0;
   int64_t tab_off = 0, tab_len = 0;  // cost tables of every family, inside ab
   int maxvpl = 1;
+  int64_t key_elems = 0;  // launch totals the shape was looked up under
+  int key_pairs = 0;
   size_t bytes(uint32_t flags = 0) const;  // device bytes; flags: HOT_FLAG_* of the problems
 };
 
@@ -109,6 +111,14 @@ struct Layout {
 // (a group of a larger batch uses the batch's entry)
 bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,
                   Layout& lay, std::string& err, int64_t key_elems = -1, int key_pairs = -1);
+void relane_layout(Layout& lay, int fp32, const Tuning& tune);
+
+// Tracks the best relative KKT of a solve for HOT_FLAG_ESCALATE.
+struct StallWatch {
+  double best = 0.0;
+  int64_t it_best = 0;
+  bool stalled(const PairCtl& c);
+};
 
 struct Workspace {
   int device = 0;
@@ -176,7 +186,8 @@ struct Workspace {
   hot_status device_buffer(hot_ctx* ctx, void** p, size_t bytes);
   hot_status alloc_all(hot_ctx* ctx);
   hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
-  hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
+  hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs,
+                 StallWatch* watch = nullptr);
   // direct launches on st, a stream synchronisation per quantum, no graph,
   // event or pinned buffer (the no-alloc entry point)
   hot_status run_direct(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
@@ -185,11 +196,16 @@ struct Workspace {
   hot_status ensure_graph(hot_ctx* ctx, hipStream_t st);
   hipError_t launch_quantum(hipStream_t st);
   hipError_t poison_state(hipStream_t st);
+  // FP32 -> FP64 streams in place (the stream is idle): the state buffers are
+  // widened exactly, the lanes re-derived, the graph re-captured
+  hot_status escalate(hot_ctx* ctx, hipStream_t st);
+  int32_t escalated_at = 0;  // iteration count at the widening, 0 if none
   // after the last graph: the feasibility error of every problem's final
   // iterate into ctl[0] (on st; copy the control blocks after it)
   hipError_t finalize(hipStream_t st);
   hipEvent_t quantum_event = nullptr;
-  hot_status run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs);
+  hot_status run_profiled(hot_ctx* ctx, hipStream_t st, int64_t max_graphs,
+                          StallWatch* watch = nullptr);
   void fill_result(int p, hot_result* r, double seconds) const;
 };
 

@@ -51,6 +51,10 @@ struct Slot {
   size_t bytes;
   int64_t quanta;
   int64_t max_quanta;
+  bool esc;          // HOT_FLAG_ESCALATE on an FP32-stream problem
+  bool esc_next;     // stalled at the last quantum: widen after this one
+  hot_status esc_err;  // a failed widening ends the request with this status
+  StallWatch watch;
 };
 
 struct Done {
@@ -166,6 +170,10 @@ static void server_loop(hot_server* S) {
       sl.bytes = bytes;
       sl.quanta = 1;
       sl.max_quanta = (int64_t)req.prob.max_iter * 2 / kGraphIters + 8;
+      sl.esc = (req.prob.flags & HOT_FLAG_ESCALATE) && req.prob.prec == HOT_FP32_STREAM &&
+               !(req.prob.flags & HOT_FLAG_FIXED_ITERS);
+      sl.esc_next = false;
+      sl.esc_err = HOT_OK;
       slots.push_back(sl);
     }
     // ---- progress of resident problems ---------------------------------
@@ -180,7 +188,20 @@ static void server_loop(hot_server* S) {
       const bool running = (e == hipSuccess) && sl.ws->host_ctl[0].status == ST_RUNNING;
       const bool cancel = S->stop.load() || sl.req.gen < S->cancel_gen.load();
       if (running && !cancel && sl.quanta < sl.max_quanta) {
-        if (sl.ws->launch_quantum(sl.ws->stream) == hipSuccess) {
+        bool ok = true;
+        if (sl.esc_next) {
+          // stalled one quantum ago: widen the state to FP64 now and continue
+          // with FP64 streams (hot_solve, which decides while its next graph
+          // is in flight, widens at the same iteration)
+          sl.esc_next = false;
+          sl.esc_err = sl.ws->escalate(&tmp, sl.ws->stream);
+          if (sl.esc_err == HOT_OK) sl.esc_err = sl.ws->ensure_graph(&tmp, sl.ws->stream);
+          ok = sl.esc_err == HOT_OK;
+          if (ok) sl.ws->escalated_at = sl.ws->host_ctl[0].it;
+        } else if (sl.esc && sl.ws->lay.fp32 && sl.watch.stalled(sl.ws->host_ctl[0])) {
+          sl.esc_next = true;
+        }
+        if (ok && sl.ws->launch_quantum(sl.ws->stream) == hipSuccess) {
           ++sl.quanta;
           ++q;
           continue;
@@ -196,6 +217,7 @@ static void server_loop(hot_server* S) {
       const double t = now_s();
       sl.ws->fill_result(0, &d.res, t - sl.req.t_submit);
       if (e != hipSuccess) d.res.status = HOT_E_DEVICE;
+      else if (sl.esc_err != HOT_OK) d.res.status = sl.esc_err;
       else if (running) d.res.status = HOT_E_CANCELLED;
       d.tag = sl.req.tag;
       d.latency = t - sl.req.t_submit;
@@ -205,7 +227,9 @@ static void server_loop(hot_server* S) {
         S->latencies.push_back(d.latency);
         ++S->completed;
         S->in_use -= sl.bytes;
-        if (S->pool_count < (size_t)(2 * S->max_slots) && e == hipSuccess) {
+        // (a workspace widened to FP64 no longer matches its FP32 key)
+        const bool same_prec = sl.ws->lay.fp32 == (sl.req.prob.prec == HOT_FP32_STREAM ? 1 : 0);
+        if (S->pool_count < (size_t)(2 * S->max_slots) && e == hipSuccess && same_prec) {
           S->pool.emplace(ShapeKey{sl.req.prob.m, sl.req.prob.n, sl.req.prob.prec},
                           std::make_pair(sl.ws, sl.bytes));
           ++S->pool_count;

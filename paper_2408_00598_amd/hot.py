@@ -18,7 +18,7 @@ HOT_OK, HOT_E_INVALID, HOT_E_NOMEM, HOT_E_DEVICE, HOT_E_NOT_CONVERGED = 0, 1, 2,
 HOT_E_BUSY, HOT_E_CANCELLED, HOT_E_NUMERIC = 5, 6, 7
 HOT_FP64, HOT_FP32_STREAM = 0, 1
 HOT_FLAG_RESTART, HOT_FLAG_FIXED_ITERS, HOT_FLAG_ADMM, HOT_FLAG_ABS_KKT = 0x1, 0x2, 0x4, 0x8
-HOT_FLAG_SIGMA_UPDATE = 0x10
+HOT_FLAG_SIGMA_UPDATE, HOT_FLAG_ESCALATE = 0x10, 0x20
 
 EXPORTED = [
     "hot_ctx_create", "hot_ctx_destroy", "hot_ctx_last_error", "hot_status_string",
@@ -48,11 +48,11 @@ class Result(C.Structure):
                 ("res_primal", C.c_double), ("res_dual", C.c_double), ("res_comp", C.c_double),
                 ("sigma", C.c_double), ("seconds", C.c_double), ("kkt_abs", C.c_double),
                 ("iters", C.c_int32),
-                ("restarts", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("restarts", C.c_int32), ("status", C.c_int32), ("escalated_at", C.c_int32),
                 ("feaserr", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None

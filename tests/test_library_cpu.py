@@ -96,7 +96,7 @@ def test_binding_flag_constants_match_header():
     text = open(os.path.join(ROOT, "include", "hot.h")).read()
     defs = dict(re.findall(r"#define (HOT_FLAG_[A-Z_]+) (0x[0-9a-f]+)u", text))
     assert set(defs) == {"HOT_FLAG_RESTART", "HOT_FLAG_FIXED_ITERS", "HOT_FLAG_ADMM",
-                         "HOT_FLAG_ABS_KKT", "HOT_FLAG_SIGMA_UPDATE"}
+                         "HOT_FLAG_ABS_KKT", "HOT_FLAG_SIGMA_UPDATE", "HOT_FLAG_ESCALATE"}
     for k, v in defs.items():
         assert getattr(hot, k) == int(v, 16), k
 
