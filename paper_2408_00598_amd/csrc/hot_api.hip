@@ -169,6 +169,7 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   if ((st = A((void**)&stats_d, lay.geo.size() * 2 * 8 * 8)) != HOT_OK) return st;
   if ((st = A((void**)&ptrs_d, lay.geo.size() * 2 * (sizeof(void*) + 8))) != HOT_OK) return st;
   if ((st = A((void**)&bytes_ctr, 256)) != HOT_OK) return st;
+  if ((st = A((void**)&sync_d, lay.geo.size() * 5 * sizeof(unsigned))) != HOT_OK) return st;
   if (arena) {
     if (arena_used > arena_bytes) {
       if (ctx)
@@ -209,6 +210,9 @@ hot_status Workspace::alloc_all(hot_ctx* ctx) {
   args.fp32 = lay.fp32;
   args.maxvpl = lay.maxvpl;
   args.bytes_ctr = bytes_ctr;
+  args.sync[0] = sync_d;
+  args.sync[1] = sync_d + 2 * lay.geo.size();
+  args.lost = sync_d + 4 * lay.geo.size();
   launch_pairs = (int)lay.geo.size();
   return HOT_OK;
 }
@@ -460,6 +464,7 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   HIPCK(hipMemcpyAsync(ab + lay.tab_off, tab_host.data(), (size_t)lay.tab_len * 8,
                        hipMemcpyHostToDevice, st));
   launch_zero(kitem, lay.items.size() * kKI * 8, st);
+  launch_zero(sync_d, lay.geo.size() * 5 * sizeof(unsigned), st);
   launch_zero(bytes_ctr, 8, st);
   HIPCK(hipGetLastError());
   // the host buffers above are pageable and the copies may still read them
@@ -865,6 +870,8 @@ static hot_status status_of(int32_t s) {
       return HOT_E_NOT_CONVERGED;
     case ST_NUMERIC:
       return HOT_E_NUMERIC;
+    case ST_SYNC_LOST:
+      return HOT_E_DEVICE;
     default:
       return HOT_E_NOT_CONVERGED;
   }
@@ -942,6 +949,8 @@ hot_status hot_ctx_create(int device, hot_ctx** out) {
   if (e) c->tune.solve_pre = std::atoi(e) != 0;
   e = std::getenv("HOT_FUSE");
   if (e) c->tune.fuse = std::atoi(e) != 0;
+  e = std::getenv("HOT_FUSE_PAIR");
+  if (e) c->tune.fuse_pair = std::atoi(e) != 0;
   e = std::getenv("HOT_BATCH_GROUPS");
   if (e) c->tune.batch_groups = std::max(1, std::min(4, std::atoi(e)));
   e = std::getenv("HOT_VPL_TARGET");
@@ -1039,6 +1048,7 @@ hot_status make_workspace(hot_ctx* ctx, const hot_problem* probs, int count,
   ws->args.nt_store = ctx->tune.nt_store;
   ws->args.fuse = ctx->tune.fuse;
   ws->args.solve_pre = ctx->tune.solve_pre;
+  ws->args.fuse_pair = ctx->tune.fuse_pair;
   // the algorithmic byte count is kept only when the passes are timed
   ws->args.bytes_ctr = ws->profile ? ws->bytes_ctr : nullptr;
   if (s != HOT_OK) return s;

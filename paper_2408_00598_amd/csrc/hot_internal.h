@@ -43,7 +43,8 @@ enum PairStatus : int32_t {
   ST_CONVERGED = 1,
   ST_MAXITER = 2,
   ST_NUMERIC = 3,
-  ST_FIXED_DONE = 4
+  ST_FIXED_DONE = 4,
+  ST_SYNC_LOST = 5  // fused reduce + solve: a wait ran out (device error)
 };
 
 // per-item partial indices (slab pass, check mode)
@@ -100,6 +101,16 @@ struct PairGeo {
   int64_t voff;          // double offset of the small vectors
   double norm_b, norm_c; // ||b||, ||c|| of the reduced model
 };
+
+// Reduce and solve workgroups of a pair: the tables list every one of a
+// running pair (the fused reduce + solve counts them).
+__host__ __device__ inline int reduce_blocks_of(const PairGeo& G) {
+  const int rq1 = G.f[0].wide ? 1 : G.rq, rq2 = G.f[1].wide ? 1 : G.rq;
+  return (G.nb1 + rq1 - 1) / rq1 + (G.nblk - G.nb1 + rq2 - 1) / rq2 + G.ns1 + G.ns2;
+}
+__host__ __device__ inline int solve_blocks_of(const PairGeo& G) {
+  return G.nsblk + G.ntj * G.ntk;
+}
 
 // M-sized arrays at moff: mu1T[j][i], mu2[k][l], R1[j][k], R2[j][i], R3T[k][l]
 __host__ __device__ inline int64_t arr_mu1T(const PairGeo& g) { return g.moff; }

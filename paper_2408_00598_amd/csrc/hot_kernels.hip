@@ -96,8 +96,10 @@ __device__ inline double wave4(const double (&w)[4][kKP], int q) {
   return (w[0][q] + w[1][q]) + (w[2][q] + w[3][q]);
 }
 
-__global__ __launch_bounds__(kWG) void k_pair_reduce(
-    const PBlock* __restrict__ blocks, const PairGeo* __restrict__ geo,
+// One reduce block's work (the body of k_pair_reduce, also the reduce role
+// of k_pair_fused).
+__device__ __forceinline__ void reduce_block(
+    const PBlock pbk, const PairGeo* __restrict__ geo,
     const PairCtl* __restrict__ ctl, const double* __restrict__ rowsum,
     const double* __restrict__ colpart, const double* __restrict__ rowsum_prev,
     const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
@@ -106,7 +108,6 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
   __shared__ double wred[4][kKP];
   __shared__ double strip[4][64];
   __shared__ double blk_red[4];
-  const PBlock pbk = blocks[blockIdx.x];
   const PairCtl* cp = ctl + pbk.pair;
   if (cp->status != ST_RUNNING) return;
   const int mode = cp->mode;
@@ -342,6 +343,17 @@ __global__ __launch_bounds__(kWG) void k_pair_reduce(
     if (threadIdx.x < kNKP)
       vec[vec_kpart(G) + (int64_t)slot * kKP + threadIdx.x] = wave4(wred, threadIdx.x);
   }
+}
+
+__global__ __launch_bounds__(kWG) void k_pair_reduce(
+    const PBlock* __restrict__ blocks, const PairGeo* __restrict__ geo,
+    const PairCtl* __restrict__ ctl, const double* __restrict__ rowsum,
+    const double* __restrict__ colpart, const double* __restrict__ rowsum_prev,
+    const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
+    const double* __restrict__ ab, double* __restrict__ abY, double* __restrict__ arr,
+    double* __restrict__ vec, unsigned long long* __restrict__ bytes_ctr, int elem) {
+  reduce_block(blocks[blockIdx.x], geo, ctl, rowsum, colpart, rowsum_prev, colpart_prev, kitem,
+               ab, abY, arr, vec, bytes_ctr, elem);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,20 +729,20 @@ __device__ __forceinline__ void solve_alpha_tile(const PairGeo& G, int tile, dou
 // (wasted only on the pass that stops the pair), waves 1-3 staging the tile
 // while wave 0 decides.  PRE = 0 issues them after it (fewer registers held
 // across the decision: 69 against 79 VGPRs).  Same arithmetic.
+// One solve block's work (the body of k_pair_solve, also the solve role of
+// k_pair_fused).
 template <int FROM_R, int PRE>
-__global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ sblocks,
-                                                    const PairGeo* __restrict__ geo,
-                                                    const PairCtl* __restrict__ ctl,
-                                                    PairCtl* __restrict__ ctl_next,
-                                                    const double* __restrict__ rowsum,
-                                                    const double* __restrict__ arr,
-                                                    const double* __restrict__ vec,
-                                                    double* __restrict__ ab) {
+__device__ __forceinline__ void solve_block(const PBlock pbk, const PairGeo* __restrict__ geo,
+                                            const PairCtl* __restrict__ ctl,
+                                            PairCtl* __restrict__ ctl_next,
+                                            const double* __restrict__ rowsum,
+                                            const double* __restrict__ arr,
+                                            const double* __restrict__ vec,
+                                            double* __restrict__ ab) {
   __shared__ PairCtl s_nx;
   __shared__ SolveScalars s_S;
   __shared__ int s_solve;
   __shared__ TileLds s_tile;
-  const PBlock pbk = sblocks[blockIdx.x];
   const bool head = (pbk.kind == 0 && pbk.blk == 0 && threadIdx.x == 0);
   if (!FROM_R) {
     const PairCtl* cp = ctl + pbk.pair;
@@ -798,6 +810,85 @@ __global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ s
   if (!FROM_R && head) ctl_next[pbk.pair] = s_nx;
 }
 
+template <int FROM_R, int PRE>
+__global__ __launch_bounds__(kWG) void k_pair_solve(const PBlock* __restrict__ sblocks,
+                                                    const PairGeo* __restrict__ geo,
+                                                    const PairCtl* __restrict__ ctl,
+                                                    PairCtl* __restrict__ ctl_next,
+                                                    const double* __restrict__ rowsum,
+                                                    const double* __restrict__ arr,
+                                                    const double* __restrict__ vec,
+                                                    double* __restrict__ ab) {
+  solve_block<FROM_R, PRE>(sblocks[blockIdx.x], geo, ctl, ctl_next, rowsum, arr, vec, ab);
+}
+
+// ---------------------------------------------------------------------------
+// Reduce and solve in one launch (HOT_FUSE_PAIR=1): workgroups [0, nblocks)
+// take the reduce blocks, the rest the solve blocks.  A reduce workgroup
+// publishes its outputs (device-scope release) and counts itself in its
+// pair's counter; a solve workgroup waits until its pair's count is complete
+// (device-scope acquire), then solves.  Every reduce workgroup has a lower
+// index than every solve workgroup, and workgroups of one launch are
+// dispatched in index order, so all reduce workgroups are dispatched before
+// any solve workgroup that could occupy their place, and the waits end.  The
+// wait is bounded all the same: past kFuseSpin polls the workgroup marks the
+// pair in `lost` and solves anyway; the finalize pass turns the mark into a
+// device error for that problem.  The last solve workgroup of a pair clears
+// its counters for the launch two iterations on (counters alternate with the
+// control-block parity).
+// ---------------------------------------------------------------------------
+constexpr unsigned kFuseSpin = 1u << 20;
+
+template <int PRE>
+__global__ __launch_bounds__(kWG) void k_pair_fused(
+    const PBlock* __restrict__ blocks, int nblocks, const PBlock* __restrict__ sblocks,
+    const PairGeo* __restrict__ geo, const PairCtl* __restrict__ ctl,
+    PairCtl* __restrict__ ctl_next, const double* __restrict__ rowsum,
+    const double* __restrict__ colpart, const double* __restrict__ rowsum_prev,
+    const double* __restrict__ colpart_prev, const double* __restrict__ kitem,
+    double* __restrict__ ab, double* __restrict__ abY, double* __restrict__ arr,
+    double* __restrict__ vec, unsigned long long* __restrict__ bytes_ctr, int elem,
+    unsigned* __restrict__ sync, unsigned* __restrict__ lost) {
+  const bool red = (int)blockIdx.x < nblocks;
+  const PBlock pbk = red ? blocks[blockIdx.x] : sblocks[blockIdx.x - nblocks];
+  const PairCtl* cp = ctl + pbk.pair;
+  const bool live = cp->status == ST_RUNNING && cp->mode != MODE_IDLE;
+  unsigned* cnt = sync + 2 * (int64_t)pbk.pair;  // (reduce count, solve count)
+  if (red) {
+    if (!live) return;
+    reduce_block(pbk, geo, ctl, rowsum, colpart, rowsum_prev, colpart_prev, kitem, ab, abY, arr,
+                 vec, bytes_ctr, elem);
+    __syncthreads();  // every wave's stores are done
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  if (live && threadIdx.x == 0) {
+    const unsigned want = (unsigned)reduce_blocks_of(geo[pbk.pair]);
+    unsigned polls = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want &&
+           ++polls < kFuseSpin)
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (polls >= kFuseSpin)
+      __hip_atomic_fetch_or(lost + pbk.pair, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  solve_block<0, PRE>(pbk, geo, ctl, ctl_next, rowsum, arr, vec, ab);
+  if (live) {
+    __syncthreads();
+    if (threadIdx.x == 0 &&
+        __hip_atomic_fetch_add(cnt + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+            (unsigned)solve_blocks_of(geo[pbk.pair]) - 1u) {
+      // every solve workgroup of the pair is past its wait
+      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(cnt + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Finalize (once per solve, after the last check): the feasibility error of
 // the experiments, max(||min(x_bar, 0)|| / (1 + ||x_bar||), res_primal), of
@@ -848,7 +939,8 @@ __global__ __launch_bounds__(kWG) void k_feas_items(const SlabItem* __restrict__
 
 __global__ __launch_bounds__(kWG) void k_feas_pairs(const PairGeo* __restrict__ geo,
                                                     PairCtl* __restrict__ ctl,
-                                                    const double* __restrict__ kitem) {
+                                                    const double* __restrict__ kitem,
+                                                    const unsigned* __restrict__ lost) {
   __shared__ double red[4];
   const PairGeo G = geo[blockIdx.x];
   double xx = 0.0, neg = 0.0;
@@ -861,6 +953,10 @@ __global__ __launch_bounds__(kWG) void k_feas_pairs(const PairGeo* __restrict__ 
   if (threadIdx.x == 0) {
     PairCtl* c = ctl + blockIdx.x;
     c->feaserr = fmax(sqrt(neg) / (1.0 + sqrt(xx)), c->res_p);
+    if (lost && lost[blockIdx.x]) {  // a fused reduce + solve wait ran out
+      c->status = ST_SYNC_LOST;
+      c->mode = MODE_IDLE;
+    }
   }
 }
 
@@ -1105,6 +1201,20 @@ static void launch_solve(const LaunchArgs& a, const PairCtl* ctl, PairCtl* ctl_n
 }
 
 void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
+  if (a.fuse_pair && a.sync[par]) {
+    const dim3 grid(a.nblocks + a.nsblocks);
+    if (a.solve_pre != 0)
+      hipLaunchKernelGGL(k_pair_fused<1>, grid, dim3(kWG), 0, st, a.blocks, a.nblocks, a.sblocks,
+                         a.geo, a.ctl[par], a.ctl[1 - par], a.rowsum[par], a.colpart[par],
+                         a.rowsum[1 - par], a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr,
+                         a.vec, a.bytes_ctr, a.fp32 ? 4 : 8, a.sync[par], a.lost);
+    else
+      hipLaunchKernelGGL(k_pair_fused<0>, grid, dim3(kWG), 0, st, a.blocks, a.nblocks, a.sblocks,
+                         a.geo, a.ctl[par], a.ctl[1 - par], a.rowsum[par], a.colpart[par],
+                         a.rowsum[1 - par], a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr,
+                         a.vec, a.bytes_ctr, a.fp32 ? 4 : 8, a.sync[par], a.lost);
+    return;
+  }
   hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
                      a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
                      a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec, a.bytes_ctr,
@@ -1112,14 +1222,11 @@ void launch_pair_kernels(const LaunchArgs& a, int par, hipStream_t st) {
   launch_solve<0>(a, a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], st);
 }
 
-// One iteration: slab pass, pair reduce, pair solve.  Reads ctl[par], writes ctl[1-par].
+// One iteration: slab pass, pair reduce, pair solve (or the two in one
+// launch).  Reads ctl[par], writes ctl[1-par].
 void launch_iteration(const LaunchArgs& a, int par, hipStream_t st) {
   launch_slab_pass(a, par, st);
-  hipLaunchKernelGGL(k_pair_reduce, dim3(a.nblocks), dim3(kWG), 0, st, a.blocks, a.geo,
-                     a.ctl[par], a.rowsum[par], a.colpart[par], a.rowsum[1 - par],
-                     a.colpart[1 - par], a.kitem, a.ab, a.abY, a.arr, a.vec, a.bytes_ctr,
-                     a.fp32 ? 4 : 8);
-  launch_solve<0>(a, a.ctl[par], a.ctl[1 - par], (const double*)a.rowsum[par], st);
+  launch_pair_kernels(a, par, st);
 }
 
 void launch_hist_stats_multi(const double* const* ptrs, const int64_t* lens, int count,
@@ -1140,7 +1247,8 @@ void launch_finalize(const LaunchArgs& a, const SlabItem* items_all, int nitems_
     hipLaunchKernelGGL(k_feas_items<double>, dim3(nitems_all), dim3(kWG), 0, st, items_all,
                        a.geo, a.ctl[0], (const double*)a.sb[0], (const double*)a.sb[1],
                        (const double*)a.sb[2], a.ab, a.kitem);
-  hipLaunchKernelGGL(k_feas_pairs, dim3(npairs), dim3(kWG), 0, st, a.geo, a.ctl[0], a.kitem);
+  hipLaunchKernelGGL(k_feas_pairs, dim3(npairs), dim3(kWG), 0, st, a.geo, a.ctl[0], a.kitem,
+                     a.lost);
 }
 
 void launch_widen(const void* in, void* out, int64_t n, hipStream_t st) {

@@ -74,6 +74,7 @@ Tuning default_tuning() {
   t.row_group = 0;
   t.reduce_group = 0;
   t.solve_pre = 1;
+  t.fuse_pair = 0;
   return t;
 }
 
@@ -91,7 +92,8 @@ size_t Layout::bytes(uint32_t flags) const {
          (size_t)cp_len * 8 * 2 + (size_t)items.size() * (kKI * 8 + sizeof(SlabItem)) +
          sitems.size() * sizeof(SmallItem) +
          (size_t)arr_len * 8 + (size_t)vec_len * 8 + geo.size() * sizeof(PairGeo) +
-         (blocks.size() + sblocks.size()) * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 + 4096;
+         (blocks.size() + sblocks.size()) * sizeof(PBlock) + geo.size() * sizeof(PairCtl) * 2 +
+         geo.size() * 5 * sizeof(unsigned) + 4096;
 }
 
 bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, const Tuning& tune,

@@ -34,6 +34,7 @@ struct Tuning {
   int row_group;        // > 0: slabs per solve wave and slots per reduce block (else by launch size)
   int reduce_group;     // > 0: slots per reduce block (overrides row_group for the reduce)
   int solve_pre;        // 1: the solve issues its decision-free loads before the decision, 0: after
+  int fuse_pair;        // 1: reduce and solve in one launch (k_pair_fused)
   // autotuned launch shapes, keyed by (precision, floor(log2) of the
   // launch's flow elements, floor(log2) of its pair count): one large pair
   // and a batch of small ones of the same total get separate entries
@@ -85,6 +86,9 @@ struct LaunchArgs {
   int su = 0;         // some pair re-balances sigma at restarts
   int fuse = 0;       // one slab kernel for plain, check and restart passes
   int solve_pre = 1;  // the solve issues its decision-free loads before the decision
+  int fuse_pair = 0;  // reduce and solve in one launch (k_pair_fused)
+  unsigned* sync[2] = {nullptr, nullptr};  // per pair (reduce count, solve count), by parity
+  unsigned* lost = nullptr;                // per pair: a fused wait ran out
   void* sbx = nullptr;      // x_bar of the last restart (sigma re-balancing), else null
   double* abY = nullptr;    // alpha / beta of the last restart (sigma re-balancing)
   unsigned long long* bytes_ctr = nullptr;  // algorithmic stream bytes of slab passes
@@ -146,6 +150,7 @@ struct Workspace {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long* bytes_ctr = nullptr;
+  unsigned* sync_d = nullptr;    // counters of the fused reduce + solve (5 per problem)
   std::vector<double> tab_host;  // cost tables uploaded by setup
   // launch tables restricted to the problems still running (a batch whose
   // problems have mostly stopped launches only the rest): device copies,

@@ -118,6 +118,8 @@ static void check(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
     CHECK(g.nsblk * 4 * g.spw >= g.m + g.n && nsol[p] == g.nsblk + g.ntj * g.ntk, "solve blocks");
     CHECK(g.ntj * 32 >= g.n && g.ntk * 32 >= g.m, "solve tiles");
     CHECK(nred[p] >= g.ns1 + g.ns2 + 1, "reduce blocks");
+    // the fused reduce + solve waits for exactly these counts
+    CHECK(nred[p] == reduce_blocks_of(g) && nsol[p] == solve_blocks_of(g), "fused counts");
   }
 }
 
