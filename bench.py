@@ -119,16 +119,15 @@ def run_serving(args):
     torch.cuda.synchronize()
     ctx = hot.Context(0)
     flags = hot.HOT_FLAG_RESTART | (hot.HOT_FLAG_SIGMA_UPDATE if args.sigma_update else 0)
-    # warm the per-shape workspaces and graphs
-    srv = hot.Server(ctx, max_slots=args.slots)
+    # warm the per-shape workspaces (or the shared groups) and graphs, then
+    # replay the trace on the same server
+    srv = hot.Server(ctx, max_slots=args.slots, shared=args.shared)
     for n in workloads.SERVE_SIDES:
         for prec, tol in ((hot.HOT_FP32_STREAM, 1e-4), (hot.HOT_FP64, 1e-6)):
             # (a few quanta only: this builds the workspaces and graphs)
             srv.submit(*pool[n][0], -1, tol=tol, prec=prec, max_iter=100, flags=flags)
     srv.drain(600.0)
     srv.poll(1024)
-    srv.close()
-    srv = hot.Server(ctx, max_slots=args.slots)
     results = []
     t0 = time.perf_counter()
 
@@ -183,7 +182,8 @@ def run_serving(args):
                                "streams) / 1e-6 (30%, "
                                + ("FP32 streams widened to FP64 on a stall" if args.fp32_first
                                   else "FP64") + "), continuous batching"
-                               + (", sigma re-balanced at restarts" if args.sigma_update else ""),
+                               + (", sigma re-balanced at restarts" if args.sigma_update else "")
+                               + (", shared launches per class" if args.shared else ""),
                    "requests": len(trace), "slots": args.slots},
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
         "offered_rate": args.rate, "completed": len(results),
@@ -192,6 +192,7 @@ def run_serving(args):
         "converged": int(sum(r["status"] == 0 for r in results)),
         "max_resident": st["max_resident"], "iters_mean": float(iters.mean()),
         "escalated": int(sum(r["escalated_at"] > 0 for r in results)),
+        "max_shared": st["max_shared"],
     }
     tight = [r for r in results if trace[r["tag"]][2] < 1e-4]
     if tight:
@@ -330,6 +331,8 @@ def main():
                     help="the generalized ADMM baseline (rho 1.7) instead of HOT")
     ap.add_argument("--escalate", action="store_true",
                     help="FP32 streams widened to FP64 when the KKT stalls (single pairs)")
+    ap.add_argument("--shared", action="store_true",
+                    help="serving: problems of one precision and side class share launches")
     ap.add_argument("--fp32-first", action="store_true",
                     help="serving: 1e-6 requests start on FP32 streams and widen to FP64 "
                          "on a stall")

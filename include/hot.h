@@ -304,6 +304,17 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
  * iterated on its own stream by its captured graph, so problems admitted at
  * different times run concurrently; iterates stay on the device until the
  * problem stops.  A problem's result equals its hot_solve result.
+ * With HOT_SERVER_SHARED in flags, problems of one precision, one side class
+ * (the larger side in 1..32, 33..48, 49..64, 65..96, 97..128, 129..192 or
+ * 193..256) and one sigma rule instead share launches: each such class has a
+ * group of max_slots slots in one set of device buffers (allocated when the
+ * class first appears, counted against the budget, kept until destroy), a
+ * problem takes a free slot at the group's next quantum boundary, and every
+ * quantum iterates all of the group's problems in the same launches.  A slot
+ * keeps the problem's own single-problem geometry, so its result is still
+ * bit-identical to hot_solve's.  Problems with HOT_FLAG_ESCALATE, larger
+ * sides, or a geometry that does not fit the class's slot run alone as
+ * above.  max_slots bounds the resident problems of all kinds together.
  * submit: non-blocking; the histograms (and grid-line positions, if any)
  *   must stay valid until its result has been polled.  HOT_E_INVALID for a malformed problem (histogram values are
  *   validated at admission and reported in the result status), HOT_E_NOMEM
@@ -312,18 +323,21 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
  *   tags and latency (submit to completion, seconds); returns how many.
  * drain: waits until every submitted problem has finished (HOT_E_BUSY on
  *   timeout).
- * stats: out[8] = completed, submitted, queued, resident, bytes resident,
- *   most resident at once, p50 latency, p99 latency (seconds).
+ * stats: out[9] = completed, submitted, queued, resident, bytes resident,
+ *   most resident at once, p50 latency, p99 latency (seconds), most problems
+ *   iterated by one shared launch.
  * cancel: every problem submitted so far ends with HOT_E_CANCELLED (queued
  *   ones at once, resident ones after their current quantum, with their last
  *   iterate's values in the result) unless it has already finished; results
  *   are polled as usual and the server keeps accepting new problems.
  * destroy: drops queued problems, stops resident ones after their current
  *   quantum (their results, not polled, are discarded), frees all. */
+#define HOT_SERVER_SHARED 0x1u /* hot_server_config.flags: shared launches */
+
 typedef struct {
   size_t hbm_budget_bytes;
   int32_t max_slots; /* 1..1024 */
-  int32_t reserved;
+  uint32_t flags;    /* HOT_SERVER_* */
 } hot_server_config;
 
 hot_status hot_server_create(hot_ctx *ctx, const hot_server_config *cfg,

@@ -472,6 +472,204 @@ hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, h
   return HOT_OK;
 }
 
+// One problem into slot s of a shared server group: the steps of setup()
+// for that problem, on the slot's ranges only (the other slots may hold
+// running problems; the stream is idle between their quanta).
+hot_status Workspace::setup_slot(hot_ctx* ctx, int s, const hot_problem& pr, const PairGeo& gin,
+                                 hipStream_t st) {
+  const size_t K = lay.geo.size();
+  PairGeo g = gin;
+  const int m = g.m, n = g.n;
+  const double* ptrs[2] = {pr.mu1, pr.mu2};
+  const int64_t lens[2] = {(int64_t)m * n, (int64_t)m * n};
+  const double** pd = (const double**)ptrs_d;
+  int64_t* ld = (int64_t*)((char*)ptrs_d + K * 2 * sizeof(void*));
+  HIPCK(hipMemcpyAsync(pd, ptrs, 2 * sizeof(void*), hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(ld, lens, 2 * 8, hipMemcpyHostToDevice, st));
+  launch_hist_stats_multi(pd, ld, 2, stats_d, st);
+  HIPCK(hipGetLastError());
+  double stats[16];
+  HIPCK(hipMemcpyAsync(stats, stats_d, sizeof(stats), hipMemcpyDeviceToHost, st));
+  std::vector<double> pos;
+  if (pr.coord_row || pr.coord_col) {
+    pos.assign((size_t)m + n, 0.0);
+    if (pr.coord_row)
+      HIPCK(hipMemcpyAsync(pos.data(), pr.coord_row, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+    if (pr.coord_col)
+      HIPCK(hipMemcpyAsync(pos.data() + m, pr.coord_col, (size_t)n * 8, hipMemcpyDeviceToHost, st));
+  }
+  HIPCK(hipStreamSynchronize(st));
+  const double* s1 = stats;
+  const double* s2 = stats + 8;
+  if (s1[2] > 0 || s2[2] > 0) {
+    ctx->err = "histogram has non-finite entries";
+    return HOT_E_INVALID;
+  }
+  if (s1[0] < 0 || s2[0] < 0) {
+    ctx->err = "histogram has negative entries";
+    return HOT_E_INVALID;
+  }
+  const double tot = std::max(s1[1], s2[1]);
+  if (!(tot > 0) || std::fabs(s1[1] - s2[1]) > 1e-9 * tot) {
+    ctx->err = "histogram totals differ or are zero";
+    return HOT_E_INVALID;
+  }
+  g.norm_b = std::sqrt(std::max(0.0, s1[3] + s2[3] - s2[4] * s2[4]));
+  // cost tables of both families, as setup() builds them
+  std::vector<double> tab[2];
+  double sq4[2];
+  for (int fam = 0; fam < 2; ++fam) {
+    const int L = g.f[fam].L;
+    const bool given = fam == 0 ? pr.coord_row != nullptr : pr.coord_col != nullptr;
+    tab[fam].assign(2 * (size_t)L + 1, 0.0);
+    double* X = tab[fam].data();
+    double* CR = X + L;
+    double cc = 0.0, q4 = 0.0;
+    for (int q = 0; q < L; ++q) X[q] = given ? pos[(fam == 0 ? 0 : m) + q] : (double)q;
+    for (int a = 0; a < L; ++a) {
+      if (given) {
+        double r = 0.0;
+        for (int q = 0; q < L; ++q) {
+          const double d = X[a] - X[q];
+          r += d * d;
+          q4 += (d * d) * (d * d);
+        }
+        CR[a] = r;
+      } else {
+        CR[a] = cost_rowsum(L, a);
+      }
+      cc += CR[a];
+    }
+    X[2 * L] = cc;
+    sq4[fam] = given ? q4 : slab_cost_sq(L);
+    if (given && (!std::isfinite(cc) || !std::isfinite(q4))) {
+      ctx->err = "grid positions must be finite";
+      return HOT_E_INVALID;
+    }
+  }
+  g.norm_c = std::sqrt((double)n * sq4[0] + (double)m * sq4[1]);
+  if (!std::isfinite(g.norm_c)) {
+    ctx->err = "cost norm overflows";
+    return HOT_E_INVALID;
+  }
+  const bool su = (pr.flags & HOT_FLAG_SIGMA_UPDATE) && (pr.flags & HOT_FLAG_RESTART) &&
+                  !(pr.flags & (HOT_FLAG_FIXED_ITERS | HOT_FLAG_ADMM));
+  if (su && !sbx) {
+    void* xbuf = nullptr;
+    void* ybuf = nullptr;
+    hot_status a = device_buffer(ctx, &xbuf, (size_t)lay.state_elems * lay.elem_size);
+    if (a == HOT_OK) a = device_buffer(ctx, &ybuf, (size_t)lay.tab_off * 8);
+    if (a != HOT_OK) return a;
+    sbx = xbuf;
+    abY = (double*)ybuf;
+  }
+  // control blocks (both parities), as setup() writes them
+  PairCtl c;
+  std::memset(&c, 0, sizeof(c));
+  c.sigma = pr.sigma > 0 ? pr.sigma : ((g.norm_c > 0 && g.norm_b > 0) ? g.norm_b / g.norm_c : 1.0);
+  c.tol = pr.tol;
+  c.lam = 0.5;
+  c.status = ST_RUNNING;
+  c.mode = MODE_INIT;
+  c.src = 0;
+  c.dst = 1;
+  c.anc = -1;
+  c.max_iter = pr.max_iter;
+  c.T = pr.check_every;
+  c.flags = (int32_t)pr.flags;
+  if (!su) c.flags &= ~(int32_t)HOT_FLAG_SIGMA_UPDATE;
+  if (ctx->tune.pingpong) c.flags |= 0x100;
+  c.relax = (pr.flags & HOT_FLAG_ADMM) ? (pr.relax > 0 ? pr.relax : 1.7) : 0.0;
+  c.sig_old = c.sigma;
+  PairCtl idle = c;
+  idle.mode = MODE_IDLE;
+  const PairCtl cs[2] = {c, idle};
+  HIPCK(hipMemcpyAsync(ctl_d + s, &cs[0], sizeof(PairCtl), hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(ctl_d + K + s, &cs[1], sizeof(PairCtl), hipMemcpyHostToDevice, st));
+  launch_setup_mu(pr.mu1, pr.mu2, m, n, arr + arr_mu1T(g), arr + arr_mu2(g), st);
+  // the slot's ranges, zero-filled by a kernel
+  const size_t es = lay.elem_size;
+  launch_zero((char*)sb[0] + (size_t)s * caps.state * es, (size_t)caps.state * es, st);
+  if (ctx->tune.sep_anchor)
+    launch_zero((char*)sb[2] + (size_t)s * caps.state * es, (size_t)caps.state * es, st);
+  for (int q = 0; q < 2; ++q) {
+    launch_zero(rowsum[q] + s * caps.rs, (size_t)caps.rs * 8, st);
+    launch_zero(colpart[q] + s * caps.cp, (size_t)caps.cp * 8, st);
+  }
+  launch_zero(ab + s * caps.ab, (size_t)caps.ab * 8, st);
+  if (su) {
+    launch_zero((char*)sbx + (size_t)s * caps.state * es, (size_t)caps.state * es, st);
+    launch_zero(abY + s * caps.ab, (size_t)caps.ab * 8, st);
+  }
+  for (int fam = 0; fam < 2; ++fam)
+    HIPCK(hipMemcpyAsync(ab + g.f[fam].xoff, tab[fam].data(), tab[fam].size() * 8,
+                         hipMemcpyHostToDevice, st));
+  launch_zero(kitem + s * caps.items * kKI, (size_t)caps.items * kKI * 8, st);
+  launch_zero(sync_d + 2 * s, 2 * sizeof(unsigned), st);
+  launch_zero(sync_d + 2 * K + 2 * s, 2 * sizeof(unsigned), st);
+  launch_zero(sync_d + 4 * K + s, sizeof(unsigned), st);
+  HIPCK(hipMemcpyAsync(geo_d + s, &g, sizeof(PairGeo), hipMemcpyHostToDevice, st));
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));  // (the host sources above are on this stack)
+  lay.geo[s] = g;
+  return HOT_OK;
+}
+
+hot_status Workspace::init_group(hot_ctx* ctx, hipStream_t st) {
+  (void)ctx;
+  const size_t K = lay.geo.size();
+  HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), K * sizeof(PairGeo), hipMemcpyHostToDevice, st));
+  launch_zero(ctl_d, 2 * K * sizeof(PairCtl), st);
+  launch_zero(sync_d, 5 * K * sizeof(unsigned), st);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));
+  return HOT_OK;
+}
+
+// Work tables of the occupied slots of a shared group (the stream is idle).
+hot_status Workspace::set_tables(hot_ctx* ctx, const std::vector<SlabItem>& items,
+                                 const std::vector<PBlock>& blocks,
+                                 const std::vector<PBlock>& sblocks, int coord, int su,
+                                 hipStream_t st) {
+  if (items.size() > lay.items.size() || blocks.size() > lay.blocks.size() ||
+      sblocks.size() > lay.sblocks.size()) {
+    ctx->err = "group tables exceed their capacity";
+    return HOT_E_INVALID;
+  }
+  if (!items.empty())
+    HIPCK(hipMemcpyAsync(items_d, items.data(), items.size() * sizeof(SlabItem),
+                         hipMemcpyHostToDevice, st));
+  if (!blocks.empty())
+    HIPCK(hipMemcpyAsync(blocks_d, blocks.data(), blocks.size() * sizeof(PBlock),
+                         hipMemcpyHostToDevice, st));
+  if (!sblocks.empty())
+    HIPCK(hipMemcpyAsync(sblocks_d, sblocks.data(), sblocks.size() * sizeof(PBlock),
+                         hipMemcpyHostToDevice, st));
+  HIPCK(hipStreamSynchronize(st));
+  int maxvpl = 1;
+  for (const SlabItem& it : items) maxvpl = std::max(maxvpl, (int)lay.geo[it.pair].f[it.fam].vpl);
+  args.items = items_d;
+  args.nitems = (int)items.size();
+  args.nbig = (int)items.size();
+  args.sitems = sitems_d;
+  args.nsitems = 0;
+  args.blocks = blocks_d;
+  args.nblocks = (int)blocks.size();
+  args.sblocks = sblocks_d;
+  args.nsblocks = (int)sblocks.size();
+  args.maxvpl = maxvpl;
+  args.coord = coord;
+  args.su = su;
+  args.sbx = su ? sbx : nullptr;
+  args.abY = su ? abY : nullptr;
+  launch_pairs = (int)lay.geo.size();
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  graph_exec = nullptr;
+  graph = nullptr;
+  return HOT_OK;
+}
+
 hot_status Workspace::escalate(hot_ctx* ctx, hipStream_t st) {
   if (!lay.fp32 || arena) return HOT_OK;
   const size_t bytes = (size_t)lay.state_elems * 8;
@@ -698,7 +896,10 @@ hot_status Workspace::run_direct(hot_ctx* ctx, hipStream_t st, int64_t max_graph
 }
 
 hipError_t Workspace::finalize(hipStream_t st) {
-  launch_finalize(args, items_d, (int)lay.items.size(), (int)lay.geo.size(), st);
+  if (group)  // the occupied slots' items (a free slot's geometry covers no item)
+    launch_finalize(args, args.items, args.nitems, (int)lay.geo.size(), st);
+  else
+    launch_finalize(args, items_d, (int)lay.items.size(), (int)lay.geo.size(), st);
   return hipGetLastError();
 }
 

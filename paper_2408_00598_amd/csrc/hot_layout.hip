@@ -246,6 +246,78 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   return true;
 }
 
+SlotCaps slot_caps(const Layout& one) {
+  SlotCaps c;
+  c.state = round_up(one.state_elems, 64);
+  c.ab = round_up(one.ab_len, 64);
+  c.rs = round_up(one.rs_len, 64);
+  c.cp = round_up(one.cp_len, 64);
+  c.arr = round_up(one.arr_len, 64);
+  c.vec = round_up(one.vec_len, 64);
+  c.items = round_up((int64_t)one.items.size(), 8);  // (kitem ranges stay 64-byte aligned)
+  c.blocks = (int64_t)one.blocks.size();
+  c.sblocks = (int64_t)one.sblocks.size();
+  return c;
+}
+
+bool slot_fits(const Layout& one, const SlotCaps& c) {
+  return one.geo.size() == 1 && one.sitems.empty() && one.state_elems <= c.state &&
+         one.ab_len <= c.ab && one.rs_len <= c.rs && one.cp_len <= c.cp && one.arr_len <= c.arr &&
+         one.vec_len <= c.vec && (int64_t)one.items.size() <= c.items &&
+         (int64_t)one.blocks.size() <= c.blocks && (int64_t)one.sblocks.size() <= c.sblocks;
+}
+
+void place_in_slot(const Layout& one, int s, const SlotCaps& c, PairGeo& g,
+                   std::vector<SlabItem>& items, std::vector<PBlock>& blocks,
+                   std::vector<PBlock>& sblocks) {
+  g = one.geo[0];
+  g.item0 += (int32_t)(s * c.items);
+  g.blk0 += (int32_t)(s * c.blocks);
+  g.sblk0 += (int32_t)(s * c.sblocks);
+  for (int fam = 0; fam < 2; ++fam) {
+    FamGeo& F = g.f[fam];
+    F.soff += s * c.state;
+    F.aboff += s * c.ab;
+    F.sumoff += s * c.ab;
+    F.xoff += s * c.ab;
+    F.rsoff += s * c.rs;
+    F.cpoff += s * c.cp;
+  }
+  g.moff += s * c.arr;
+  g.voff += s * c.vec;
+  items = one.items;
+  for (SlabItem& it : items) {
+    it.pair = s;
+    it.kslot += (int32_t)(s * c.items);
+  }
+  blocks = one.blocks;
+  for (PBlock& b : blocks) b.pair = s;
+  sblocks = one.sblocks;
+  for (PBlock& b : sblocks) b.pair = s;
+}
+
+void group_layout(const SlotCaps& c, int K, int fp32, Layout& lay) {
+  lay = Layout();
+  lay.fp32 = fp32;
+  lay.elem_size = fp32 ? 4 : 8;
+  PairGeo zero;
+  std::memset(&zero, 0, sizeof(zero));
+  lay.geo.assign(K, zero);
+  lay.items.assign(K * c.items, SlabItem{0, 0, 0, 0, 0, 0, 0, 0});
+  lay.nbig = (int64_t)lay.items.size();
+  lay.blocks.assign(K * c.blocks, PBlock{0, 0, 0, 0});
+  lay.sblocks.assign(K * c.sblocks, PBlock{0, 0, 0, 0});
+  lay.state_elems = K * c.state;
+  lay.ab_len = K * c.ab;
+  lay.tab_off = lay.ab_len;  // (sigma re-balancing keeps a copy of all of it)
+  lay.tab_len = 0;
+  lay.rs_len = K * c.rs;
+  lay.cp_len = K * c.cp;
+  lay.arr_len = K * c.arr;
+  lay.vec_len = K * c.vec;
+  lay.maxvpl = 1;
+}
+
 // Lanes of every family for streams of another precision on the same pitches,
 // offsets and row chunks: when a solve's FP32 state is widened to FP64 in
 // place, the elements per 16-byte vector change and the buffer geometry does

@@ -117,6 +117,25 @@ bool build_layout(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
                   Layout& lay, std::string& err, int64_t key_elems = -1, int key_pairs = -1);
 void relane_layout(Layout& lay, int fp32, const Tuning& tune);
 
+// Slots of a shared server group: every slot holds one problem at fixed
+// bases in the group's arrays, with the geometry and work tables its own
+// single-problem layout gives it (so its kernels and reduction order are
+// those of a solve alone).  A slot's capacities are the array lengths and
+// table sizes of the single-problem layout of the group's largest shape.
+struct SlotCaps {
+  int64_t state = 0, ab = 0, rs = 0, cp = 0, arr = 0, vec = 0;
+  int64_t items = 0, blocks = 0, sblocks = 0;
+};
+SlotCaps slot_caps(const Layout& one);
+bool slot_fits(const Layout& one, const SlotCaps& c);
+// the single problem of `one` placed in slot s: its geometry with every
+// offset moved to the slot's bases, and its work-table entries
+void place_in_slot(const Layout& one, int s, const SlotCaps& c, PairGeo& g,
+                   std::vector<SlabItem>& items, std::vector<PBlock>& blocks,
+                   std::vector<PBlock>& sblocks);
+// arrays and tables of a group of K slots (geometry zero until slots fill)
+void group_layout(const SlotCaps& c, int K, int fp32, Layout& lay);
+
 // Tracks the best relative KKT of a solve for HOT_FLAG_ESCALATE.
 struct StallWatch {
   double best = 0.0;
@@ -191,6 +210,19 @@ struct Workspace {
   hot_status device_buffer(hot_ctx* ctx, void** p, size_t bytes);
   hot_status alloc_all(hot_ctx* ctx);
   hot_status setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st);
+  // shared server groups: set up problem `pr` in slot s (geometry g from
+  // place_in_slot; the stream is idle), and install the work tables of the
+  // occupied slots (re-captured into the graph on the next ensure_graph)
+  bool group = false;
+  SlotCaps caps;
+  hot_status setup_slot(hot_ctx* ctx, int s, const hot_problem& pr, const PairGeo& g,
+                        hipStream_t st);
+  // a new group: every slot's geometry zero (covering no item), control
+  // blocks and fused-launch counters cleared, before any slot is used
+  hot_status init_group(hot_ctx* ctx, hipStream_t st);
+  hot_status set_tables(hot_ctx* ctx, const std::vector<SlabItem>& items,
+                        const std::vector<PBlock>& blocks, const std::vector<PBlock>& sblocks,
+                        int coord, int su, hipStream_t st);
   hot_status run(hot_ctx* ctx, hipStream_t st, int64_t max_graphs,
                  StallWatch* watch = nullptr);
   // direct launches on st, a stream synchronisation per quantum, no graph,

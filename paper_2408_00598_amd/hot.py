@@ -19,6 +19,7 @@ HOT_E_BUSY, HOT_E_CANCELLED, HOT_E_NUMERIC = 5, 6, 7
 HOT_FP64, HOT_FP32_STREAM = 0, 1
 HOT_FLAG_RESTART, HOT_FLAG_FIXED_ITERS, HOT_FLAG_ADMM, HOT_FLAG_ABS_KKT = 0x1, 0x2, 0x4, 0x8
 HOT_FLAG_SIGMA_UPDATE, HOT_FLAG_ESCALATE = 0x10, 0x20
+HOT_SERVER_SHARED = 0x1
 
 EXPORTED = [
     "hot_ctx_create", "hot_ctx_destroy", "hot_ctx_last_error", "hot_status_string",
@@ -33,7 +34,7 @@ EXPORTED = [
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_uint32)]
 
 
 class Problem(C.Structure):
@@ -373,9 +374,10 @@ class Solution:
 class Server:
     """Continuous-batching service on one context (hot_server_*)."""
 
-    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 8):
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_slots: int = 8,
+                 shared: bool = False):
         self.ctx = ctx
-        cfg = ServerConfig(hbm_budget_bytes, max_slots, 0)
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, HOT_SERVER_SHARED if shared else 0)
         h = C.c_void_p()
         st = lib().hot_server_create(ctx.h, C.byref(cfg), C.byref(h))
         if st != HOT_OK:
@@ -414,10 +416,10 @@ class Server:
         return lib().hot_server_drain(self.h, timeout)
 
     def stats(self):
-        out = (C.c_double * 8)()
+        out = (C.c_double * 9)()
         lib().hot_server_stats(self.h, out)
         keys = ["completed", "submitted", "queued", "resident", "bytes_resident",
-                "max_resident", "p50", "p99"]
+                "max_resident", "p50", "p99", "max_shared"]
         return dict(zip(keys, list(out)))
 
     def close(self):

@@ -123,6 +123,74 @@ static void check(const std::vector<std::pair<int, int>>& shapes, int fp32, cons
   }
 }
 
+// A shared server group: problems placed in slots of the class's capacity
+// keep their own geometry, lie inside their slot's ranges and never overlap
+// another slot.
+static void check_group(int side, int fp32, const Tuning& tune) {
+  Layout cap, grp;
+  std::string err;
+  CHECK(build_layout({{side, side}}, fp32, tune, cap, err), "class layout");
+  const SlotCaps c = slot_caps(cap);
+  const int K = 5;
+  group_layout(c, K, fp32, grp);
+  CHECK(grp.state_elems == K * c.state && grp.ab_len == K * c.ab &&
+            (int64_t)grp.items.size() == K * c.items,
+        "group capacities");
+  CHECK(c.state % 64 == 0 && c.ab % 64 == 0 && c.items % 8 == 0, "slot alignment");
+  // a slot not yet used covers no item (the finalize pass visits every slot)
+  for (const PairGeo& z : grp.geo) CHECK(z.item0 == 0 && z.nitem == 0, "empty slot geometry");
+  const std::pair<int, int> shapes[] = {{side, side}, {side / 2 + 1, side}, {side, 3},
+                                        {1, 1}, {side - 1, side / 3 + 1}};
+  std::vector<Range> st, abr, rs, cp, mr, vr, it;
+  int placed = 0;
+  for (int s = 0; s < K; ++s) {
+    Layout one;
+    CHECK(build_layout({shapes[s]}, fp32, tune, one, err), "slot layout");
+    if (!slot_fits(one, c)) continue;  // (runs alone instead)
+    PairGeo g;
+    std::vector<SlabItem> items;
+    std::vector<PBlock> blocks, sblocks;
+    place_in_slot(one, s, c, g, items, blocks, sblocks);
+    ++placed;
+    const PairGeo& g0 = one.geo[0];
+    CHECK(g.m == g0.m && g.n == g0.n && g.nitem == g0.nitem && g.nblk == g0.nblk &&
+              reduce_blocks_of(g) == (int)blocks.size() && solve_blocks_of(g) == (int)sblocks.size(),
+          "slot geometry");
+    for (const SlabItem& x : items)
+      CHECK(x.pair == s && x.kslot >= g.item0 && x.kslot < g.item0 + g.nitem &&
+                x.kslot < (s + 1) * c.items,
+            "slot item");
+    for (const PBlock& b : blocks) CHECK(b.pair == s, "slot reduce block");
+    for (const PBlock& b : sblocks) CHECK(b.pair == s, "slot solve block");
+    it.push_back({g.item0, g.item0 + g.nitem});
+    mr.push_back({g.moff, g.moff + 5 * (int64_t)g.m * g.n});
+    vr.push_back({g.voff, g.voff + vec_size(g)});
+    for (int fam = 0; fam < 2; ++fam) {
+      const FamGeo& F = g.f[fam];
+      const FamGeo& F0 = g0.f[fam];
+      CHECK(F.L == F0.L && F.P == F0.P && F.rpc == F0.rpc && F.nchunk == F0.nchunk &&
+                F.vpl == F0.vpl && F.lrs == F0.lrs && F.soff % 64 == 0,
+            "slot family geometry");
+      st.push_back({F.soff, F.soff + (int64_t)F.nslab * F.L * F.P});
+      abr.push_back({F.aboff, F.aboff + (int64_t)F.nslab * 2 * F.L});
+      abr.push_back({F.sumoff, F.sumoff + (int64_t)F.nslab * 2});
+      abr.push_back({F.xoff, F.xoff + 2 * (int64_t)F.L + 1});
+      rs.push_back({F.rsoff, F.rsoff + (int64_t)F.nslab * F.L});
+      cp.push_back({F.cpoff, F.cpoff + (int64_t)F.nslab * F.nchunk * F.L});
+      CHECK(F.soff >= s * c.state && F.soff + (int64_t)F.nslab * F.L * F.P <= (s + 1) * c.state,
+            "slot state range");
+      CHECK(F.xoff + 2 * (int64_t)F.L + 1 <= (s + 1) * c.ab && F.aboff >= s * c.ab,
+            "slot alpha/beta range");
+      CHECK(F.cpoff + (int64_t)F.nslab * F.nchunk * F.L <= (s + 1) * c.cp, "slot partial range");
+    }
+  }
+  CHECK(placed >= 4, "only %d of %d shapes fit a slot of side %d", placed, K, side);
+  for (const auto* v : {&st, &abr, &rs, &cp, &mr, &vr, &it}) CHECK(disjoint(*v), "slots overlap");
+  for (const Range& r : st) CHECK(r.hi <= grp.state_elems, "group state range");
+  for (const Range& r : mr) CHECK(r.hi <= grp.arr_len, "group M-array range");
+  for (const Range& r : vr) CHECK(r.hi <= grp.vec_len, "group vector range");
+}
+
 int main() {
   std::vector<std::pair<int, int>> sides = {{1, 1},   {1, 2},   {2, 1},    {3, 17},   {17, 3},
                                             {32, 32}, {48, 48}, {65, 33},  {100, 3},  {128, 128},
@@ -144,6 +212,8 @@ int main() {
       check(batch, fp32, t);
       check({{1, 1}, {1024, 1}, {1, 1024}, {7, 7}}, fp32, t);
     }
+  for (int fp32 = 0; fp32 < 2; ++fp32)
+    for (int side : {32, 48, 64, 96, 128, 192, 256}) check_group(side, fp32, default_tuning());
   // invalid sides are refused, not laid out
   Layout lay;
   std::string err;

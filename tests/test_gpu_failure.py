@@ -34,11 +34,12 @@ def test_nan_in_state_gives_numeric(monkeypatch, prec):
     assert ok["status"] == 0
 
 
-def test_server_cancel():
+@pytest.mark.parametrize("shared", [False, True])
+def test_server_cancel(shared):
     need_gpu()
     from paper_2408_00598_amd import hot, workloads
     c = hot.Context(0)
-    srv = hot.Server(c, max_slots=2)
+    srv = hot.Server(c, max_slots=2, shared=shared)
     keep = []
     for t in range(6):  # two resident, four queued; none can finish soon
         a, b = (dev(x) for x in workloads.pair_medium("blobs", pair=t, n=64))

@@ -64,3 +64,64 @@ def test_server_admission_respects_budget():
     with pytest.raises(hot.HotError):
         srv.submit(*keep[0], 99, tol=1e-5)
     srv.close()
+
+
+def test_server_shared_launches_equal_alone():
+    """HOT_SERVER_SHARED: problems of one class iterate in the same launches
+    (slots of one group, joined at quantum boundaries while others run), and
+    each result is still bit-identical to its solo hot_solve result."""
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    c = ctx()
+    srv = hot.Server(c, hbm_budget_bytes=0, max_slots=5, shared=True)
+    rng = np.random.default_rng(21)
+    reqs = []
+    shapes = [(32, 32), (24, 24), (17, 30), (32, 32), (40, 40), (48, 33), (64, 64), (60, 50),
+              (32, 9), (20, 20), (64, 64), (45, 48)]
+    for t, (m, n) in enumerate(shapes):
+        a = workloads.gaussian_blobs(m, n, 2, rng)
+        b = workloads.gaussian_blobs(m, n, 3, rng)
+        tol = 1e-4 if t % 3 else 1e-6
+        prec = hot.HOT_FP32_STREAM if t % 2 else hot.HOT_FP64
+        flags = hot.HOT_FLAG_RESTART | (hot.HOT_FLAG_SIGMA_UPDATE if t % 5 == 4 else 0)
+        reqs.append((t, dev(a), dev(b), tol, prec, flags))
+    for q, (t, a, b, tol, prec, flags) in enumerate(reqs):
+        srv.submit(a, b, t, tol=tol, prec=prec, max_iter=200000, flags=flags)
+        if q in (3, 7):
+            time.sleep(0.02)  # later arrivals join groups that are running
+    assert srv.drain(300.0) == hot.HOT_OK
+    got = {r["tag"]: r for r in srv.poll(64)}
+    st = srv.stats()
+    srv.close()
+    assert len(got) == len(reqs)
+    assert st["max_shared"] >= 2 and st["max_resident"] <= 5
+    for t, a, b, tol, prec, flags in reqs:
+        alone, _ = c.solve(a, b, tol=tol, prec=prec, max_iter=200000, flags=flags)
+        r = got[t]
+        assert r["status"] == hot.HOT_OK, (t, r["status"])
+        for key in ("primal_obj", "dual_obj", "kkt", "kkt_abs", "feaserr", "iters", "restarts",
+                    "status"):
+            assert r[key] == alone[key], (t, key, r[key], alone[key])
+
+
+def test_server_shared_slots_reused():
+    """More same-class requests than slots: slots are freed and reused at
+    quantum boundaries; every result equals its solo result."""
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    c = ctx()
+    srv = hot.Server(c, max_slots=2, shared=True)
+    pairs = []
+    for t in range(7):
+        a, b = workloads.serving_pair(64, workloads.seed_for(9, t))
+        pairs.append((dev(a), dev(b)))
+        srv.submit(*pairs[-1], t, tol=1e-4, prec=hot.HOT_FP32_STREAM, max_iter=100000)
+    assert srv.drain(300.0) == hot.HOT_OK
+    got = {r["tag"]: r for r in srv.poll(64)}
+    st = srv.stats()
+    srv.close()
+    assert st["max_shared"] == 2 and st["max_resident"] <= 2
+    for t, (a, b) in enumerate(pairs):
+        alone, _ = c.solve(a, b, tol=1e-4, prec=hot.HOT_FP32_STREAM, max_iter=100000)
+        for key in ("primal_obj", "kkt", "iters", "feaserr", "status"):
+            assert got[t][key] == alone[key], (t, key)

@@ -99,6 +99,8 @@ def test_binding_flag_constants_match_header():
                          "HOT_FLAG_ABS_KKT", "HOT_FLAG_SIGMA_UPDATE", "HOT_FLAG_ESCALATE"}
     for k, v in defs.items():
         assert getattr(hot, k) == int(v, 16), k
+    srv = re.search(r"#define HOT_SERVER_SHARED (0x[0-9a-f]+)u", text)
+    assert srv and hot.HOT_SERVER_SHARED == int(srv.group(1), 16)
 
 
 @pytest.mark.parametrize("name,cname", [("Params", "or_params"), ("Result", "or_result")])
