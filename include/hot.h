@@ -194,9 +194,15 @@ hot_status hot_autotune(hot_ctx *ctx, const hot_problem *probs, int32_t count,
                         int32_t iters, const char *cache_path, double *out);
 hot_status hot_autotune_load(hot_ctx *ctx, const char *cache_path);
 
-/* Device bytes one problem needs (state buffers, sums, dual vectors).
- * Pure host arithmetic; 0 for invalid sizes. */
+/* Device bytes one problem needs (state buffers, sums, dual vectors), laid
+ * out with the built-in launch-shape rule.  Pure host arithmetic; 0 for
+ * invalid sizes. */
 size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags);
+/* The same with the context's launch-shape tuning (environment overrides and
+ * loaded autotuner choices), which is what hot_solve allocates and what the
+ * server admits by. */
+size_t hot_ctx_footprint_bytes(hot_ctx *ctx, int32_t m, int32_t n, int32_t prec,
+                               uint32_t flags);
 
 /* Upper bound on the number of plan entries hot_recover_plan may write:
  * m*n*(m+n-1) from Algorithm 1 plus 2*m*n - 1 from the marginal repair. */
@@ -296,7 +302,7 @@ hot_status hot_batch_wait(hot_batch *batch, hot_result *results);
 
 /* Continuous-batching service.  A worker thread admits queued problems
  * (FIFO) whenever fewer than max_slots are resident and the sum of their
- * device footprints (hot_footprint_bytes) stays within hbm_budget_bytes
+ * device footprints (hot_ctx_footprint_bytes) stays within hbm_budget_bytes
  * (0: 80% of the free device memory at creation; footprints are computed
  * with the context's launch-shape tuning, and workspaces kept for reuse after
  * a problem finishes count against the budget until they are freed to admit

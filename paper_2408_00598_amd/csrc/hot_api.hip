@@ -1200,6 +1200,14 @@ size_t hot_footprint_bytes(int32_t m, int32_t n, int32_t prec, uint32_t flags) {
   return lay.bytes(flags);
 }
 
+size_t hot_ctx_footprint_bytes(hot_ctx* ctx, int32_t m, int32_t n, int32_t prec, uint32_t flags) {
+  Layout lay;
+  std::string err;
+  if (!ctx || (prec != HOT_FP64 && prec != HOT_FP32_STREAM)) return 0;
+  if (!build_layout({{m, n}}, prec == HOT_FP32_STREAM, ctx->tune, lay, err)) return 0;
+  return lay.bytes(flags);
+}
+
 int64_t hot_plan_capacity(int32_t m, int32_t n) {
   if (m < 1 || n < 1) return 0;
   const int64_t M = (int64_t)m * n;

@@ -23,7 +23,7 @@ HOT_SERVER_SHARED = 0x1
 
 EXPORTED = [
     "hot_ctx_create", "hot_ctx_destroy", "hot_ctx_last_error", "hot_status_string",
-    "hot_footprint_bytes", "hot_plan_capacity", "hot_solve", "hot_solution_export",
+    "hot_footprint_bytes", "hot_ctx_footprint_bytes", "hot_plan_capacity", "hot_solve", "hot_solution_export",
     "hot_solution_free", "hot_recover_plan", "hot_aat_solve", "hot_batch_submit",
     "hot_batch_wait", "hot_server_create", "hot_server_submit", "hot_server_poll",
     "hot_server_stats", "hot_server_destroy", "hot_server_drain", "hot_ctx_set_profiling",
@@ -82,6 +82,8 @@ def lib():
     L.hot_status_string.restype = C.c_char_p
     L.hot_footprint_bytes.argtypes = [i32, i32, i32, C.c_uint32]
     L.hot_footprint_bytes.restype = C.c_size_t
+    L.hot_ctx_footprint_bytes.argtypes = [vp, i32, i32, i32, C.c_uint32]
+    L.hot_ctx_footprint_bytes.restype = C.c_size_t
     L.hot_plan_capacity.argtypes = [i32, i32]
     L.hot_plan_capacity.restype = i64
     L.hot_solve.argtypes = [vp, C.POINTER(Problem), vp, C.POINTER(vp), C.POINTER(Result)]
@@ -203,6 +205,10 @@ class Context:
                        None if cv is None else cv.data_ptr())
         prob._keep = (mu1, mu2, cu, cv)
         return prob
+
+    def footprint_bytes(self, m, n, prec=HOT_FP64, flags=HOT_FLAG_RESTART):
+        """Device bytes of one problem under this context's launch-shape tuning."""
+        return int(lib().hot_ctx_footprint_bytes(self.h, m, n, prec, flags))
 
     def solve(self, mu1, mu2, keep=False, stream=None, raise_on_error=True, **kw):
         """Run hot_solve; returns (result dict, Solution or None)."""

@@ -59,6 +59,27 @@ def test_server_admission_respects_budget():
     srv.close()
     assert len(res) == 5 and all(r["status"] == 0 for r in res)
     assert st["max_resident"] == 2
+    # mixed shapes and precisions, admitted by the context's footprints:
+    # any three of them exceed the budget, any two fit
+    shapes = [(48, 48, hot.HOT_FP64), (32, 40, hot.HOT_FP32_STREAM), (40, 24, hot.HOT_FP64),
+              (44, 44, hot.HOT_FP32_STREAM)]
+    fps = sorted(c.footprint_bytes(m, n, p) for m, n, p in shapes)
+    assert all(f > 0 for f in fps)
+    budget = fps[-1] + fps[-2]
+    assert fps[0] + fps[1] + fps[2] > budget
+    srv = hot.Server(c, hbm_budget_bytes=budget, max_slots=8)
+    rng = np.random.default_rng(5)
+    keep2 = []
+    for t, (m, n, p) in enumerate(shapes):
+        a, b = dev(workloads.gaussian_blobs(m, n, 2, rng)), dev(workloads.gaussian_blobs(m, n, 2, rng))
+        keep2.append((a, b))
+        srv.submit(a, b, t, tol=1e-5, prec=p, max_iter=200000)
+    assert srv.drain(300.0) == hot.HOT_OK
+    res = srv.poll(16)
+    st = srv.stats()
+    srv.close()
+    assert len(res) == 4 and all(r["status"] == 0 for r in res)
+    assert st["max_resident"] <= 2
     # a problem larger than the whole budget is refused at submission
     srv = hot.Server(c, hbm_budget_bytes=fp // 2, max_slots=2)
     with pytest.raises(hot.HotError):
