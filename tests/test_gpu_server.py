@@ -61,8 +61,8 @@ def test_server_admission_respects_budget():
     assert st["max_resident"] == 2
     # mixed shapes and precisions, admitted by the context's footprints:
     # any three of them exceed the budget, any two fit
-    shapes = [(48, 48, hot.HOT_FP64), (32, 40, hot.HOT_FP32_STREAM), (40, 24, hot.HOT_FP64),
-              (44, 44, hot.HOT_FP32_STREAM)]
+    shapes = [(40, 40, hot.HOT_FP64), (36, 44, hot.HOT_FP64), (44, 36, hot.HOT_FP64),
+              (52, 50, hot.HOT_FP32_STREAM)]
     fps = sorted(c.footprint_bytes(m, n, p) for m, n, p in shapes)
     assert all(f > 0 for f in fps)
     budget = fps[-1] + fps[-2]
