@@ -50,6 +50,8 @@ namespace {
 constexpr int kScanBlock = 1024;  // elements per block of the scans
 constexpr int kRecWaves = 4;      // waves (bin units) per workgroup of the bin passes
 constexpr int kNwSpan = 16;       // merged breakpoints per thread of the deficit coupling
+// the write pass keeps one bit per merged position of a lane: (m + n) / 64 <= 32
+static_assert(2 * kMaxSide <= 64 * 32, "merged positions per lane exceed 32");
 
 __device__ inline double wave_sum_r(double v) {
 #pragma unroll
@@ -152,29 +154,43 @@ __device__ inline RowRef<T> row_ref(const T* s, const double* ab, const FamGeo& 
 
 // The row's clipped flows of the lane's block (0 past L).  BPRE: beta from
 // bpre[] (preloaded for the slab a unit keeps), else from memory.  UNI:
-// uniform grid.
+// uniform grid.  Every load is issued unconditionally (lanes past the row
+// read element 0 and discard it), so the block's loads are in flight
+// together: loads under a per-element branch each waited for their data.
 template <typename T, int MAXB, bool UNI, bool BPRE>
 __device__ inline void load_row(const RowRef<T>& row, int L, int B, double sigma,
                                 const double* bpre, int lane, double (&v)[MAXB]) {
   const int q0 = lane * B;
+  T sv[MAXB];
+  double bq[MAXB], xq[MAXB];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int q = q0 + b;
-    v[b] = 0.0;
-    if (b < B && q < L) {
-      const double d = UNI ? (double)(row.p - q) : row.xp - row.X[q];
-      const double bq = BPRE ? bpre[b] : row.beta[q];
-      v[b] = clip_flow((double)row.s[q], d, row.ap, bq, sigma);
-    }
+    const int qc = (b < B && q < L) ? q : 0;
+    sv[b] = row.s[qc];
+    bq[b] = BPRE ? bpre[b] : row.beta[qc];
+    xq[b] = UNI ? 0.0 : row.X[qc];
+  }
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int q = q0 + b;
+    const double d = UNI ? (double)(row.p - q) : row.xp - xq[b];
+    v[b] = (b < B && q < L) ? clip_flow((double)sv[b], d, row.ap, bq[b], sigma) : 0.0;
   }
 }
 
 template <int MAXB>
 __device__ inline void preload(const double* src, int L, int B, int lane, double (&out)[MAXB]) {
+  double raw[MAXB];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int q = lane * B + b;
-    out[b] = (b < B && q < L) ? src[q] : 0.0;
+    raw[b] = src[(b < B && q < L) ? q : 0];
+  }
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int q = lane * B + b;
+    out[b] = (b < B && q < L) ? raw[b] : 0.0;
   }
 }
 
@@ -482,6 +498,8 @@ __global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
     load_row<T, MAXB, UNI, false>(row_ref<T>(s, A.ab, G.f[1], k, j), n, Bn, c.sigma, nullptr, lane,
                                   vb);
     const double* C = rho_c + (int64_t)k * n;  // column factors of targets (k, l)
+    double Cl[MAXB];                           // (the lane's block of them)
+    preload<MAXB>(C, n, Bn, lane, Cl);
     (void)block_totals<MAXB>(va, m, Bm, lane, ph, plo);
     stage<MAXB>(ph, m, Bm, P, lane);
     const double QT = block_totals<MAXB>(vb, n, Bn, lane, qh, qlo);
@@ -491,7 +509,7 @@ __global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
 #pragma unroll
       for (int b = 0; b < MAXB; ++b) {
         const int l = lane * Bn + b;
-        cw[b] = (b < Bn && l < n) ? vb[b] * C[l] : 0.0;
+        cw[b] = (b < Bn && l < n) ? vb[b] * Cl[b] : 0.0;
       }
       block_sums<MAXB>(cw, gs);
       stage<MAXB>(gs, n, Bn, Gq, lane);
@@ -512,10 +530,14 @@ __global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
         if (t > 0.0) cur = advance(Q, n, cur, t);
         cb[b] = cur;
       }
-      const double w0 = (t0 > 0.0 && c0 < n) ? C[c0] : 0.0;
+      // (unconditional loads at clamped indices, selected afterwards)
+      const double w0r = C[c0 < n ? c0 : 0];
       double wb[MAXB];
 #pragma unroll
-      for (int b = 0; b < MAXB; ++b) wb[b] = cb[b] < n ? C[cb[b]] : 0.0;
+      for (int b = 0; b < MAXB; ++b) wb[b] = C[cb[b] < n ? cb[b] : 0];
+      const double w0 = (t0 > 0.0 && c0 < n) ? w0r : 0.0;
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) wb[b] = cb[b] < n ? wb[b] : 0.0;
       double glo = t0 <= 0.0 ? 0.0 : (c0 < n ? Gq[c0] + (t0 - Q[c0]) * w0 : Gq[n]);
 #pragma unroll
       for (int b = 0; b < MAXB; ++b) {
@@ -543,30 +565,32 @@ __global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
       bq = kb - lo;
     }
     const double u0 = fmax(P[a], Q[bq]);
-    int cnt = 0;
+    // one walk over the lane's S <= 32 merged positions: bit t of `src`
+    // says the step took a source total, bit t of `ent` that it ends a
+    // positive segment (an entry); the keys are then emitted from the bits
+    // alone, after the wave scan of the counts
+    unsigned src = 0u, ent = 0u;
     {
       int aa = a, bb = bq;
       double uu = u0;
       for (int t = kb; t < ke; ++t) {
         const bool takeP = aa < m && (bb >= n || P[aa + 1] <= Q[bb + 1]);
         const double e = takeP ? P[aa + 1] : Q[bb + 1];
-        if (e > uu && aa < m && bb < n) ++cnt;
+        if (e > uu && aa < m && bb < n) ent |= 1u << (t - kb);
+        if (takeP) src |= 1u << (t - kb);
         uu = e;
         if (takeP) ++aa; else ++bb;
       }
     }
+    const int cnt = __builtin_popcount(ent);
     const int incl = wave_incl_sum_i(cnt);
     const int total = readlane_i(incl, 63);
     {  // the bin's (source, target) pairs into LDS, in walk order
       int pos = incl - cnt;
       int aa = a, bb = bq;
-      double uu = u0;
-      for (int t = kb; t < ke; ++t) {
-        const bool takeP = aa < m && (bb >= n || P[aa + 1] <= Q[bb + 1]);
-        const double e = takeP ? P[aa + 1] : Q[bb + 1];
-        if (e > uu && aa < m && bb < n) K[pos++] = ((unsigned)aa << 16) | (unsigned)bb;
-        uu = e;
-        if (takeP) ++aa; else ++bb;
+      for (int t = 0; t < ke - kb; ++t) {
+        if ((ent >> t) & 1u) K[pos++] = ((unsigned)aa << 16) | (unsigned)bb;
+        if ((src >> t) & 1u) ++aa; else ++bb;
       }
     }
     wave_lds_sync();
@@ -582,8 +606,10 @@ __global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int e = e0 + 64 * q + lane;
-        key[q] = e < total ? K[e] : 0u;
+        key[q] = K[e < total ? e : 0];
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) key[q] = e0 + 64 * q + lane < total ? key[q] : 0u;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         rf[q] = Rg[key[q] >> 16];
