@@ -282,11 +282,19 @@ void or_kkt_xy(int32_t m, int32_t n, const double *cu, const double *cv,
   free(c); free(b); free(v); free(r);
 }
 
-/* Algorithm 2 (alg:HOT) in the variables w = (y, z, x), with
- *   Step 1 from eq. update:y solved by Prop. 3,
- *   Step 2 x_bar = x + sigma (A^T y_bar + z - c),
- *   Step 3 z_bar = Pi_+(c - A^T y_bar - x_bar/sigma),
- *   Step 4 Halpern step with weight 1/(k+2) toward w^0.
+/* Algorithm 2 (alg:HOT) in the variables w = (y, z, x).  On the dual of the
+ * reduced model (maximise b^T y subject to A^T y + z = c, z >= 0), x is the
+ * multiplier of the equality and sigma its penalty; with the augmented
+ * Lagrangian -b^T y + <x, A^T y + z - c> + (sigma/2) ||A^T y + z - c||^2:
+ *   Step 1 minimises it over y (z, x held): setting its gradient to zero
+ *     gives A A^T y_bar = b/sigma - A(x/sigma + z - c) (eq. update:y),
+ *     solved by Prop. 3;
+ *   Step 2 moves the multiplier along the residual at (y_bar, z):
+ *     x_bar = x + sigma (A^T y_bar + z - c);
+ *   Step 3 minimises it over z >= 0 with the new multiplier: the free
+ *     minimiser c - A^T y_bar - x_bar/sigma, projected onto z >= 0;
+ *   Step 4 averages the pass's output with the epoch's anchor w^0
+ *     (Halpern weight 1/(k+2)).
  * Readings where the paper is silent: w^0 = 0; sigma = ||b||/||c|| unless
  * given; the check runs every T iterations of the current epoch (k % T == 0)
  * and evaluates eq. kkt_res at w_bar^k; with restarts on, the epoch restarts
@@ -453,39 +461,59 @@ int32_t or_hot(int32_t m, int32_t n, const double *mu1, const double *mu2,
   return converged;
 }
 
-/* Algorithm 1 (alg:transportplan) applied to the clipped flows max(x, 0):
- * for every bin (k,j), the incoming column flows f1_{.,k,j} are matched
- * against the outgoing row flows f2_{k,j,.} in the order i = 1..m, l = 1..n,
- * each match taking the smaller of the two remaining amounts.  Entries with
- * positive mass are written as (source bin i*n+j, target bin k*n+l, mass).
- * Returns the number of entries (which may exceed cap: then only the first
- * cap entries are stored). */
+/* The plan of Algorithm 1 (alg:transportplan) from the clipped flows
+ * f = max(x, 0).  Bin (k,j) receives the mass f1_{i,k,j} from each source
+ * bin (i,j) of its column and sends f2_{k,j,l} to each target bin (k,l) of
+ * its row; flow conservation at the bin (Prop. 1) makes the two totals
+ * equal for an optimal flow.  Algorithm 1 pairs the two sequences greedily
+ * in their natural order, i ascending against l ascending, always moving
+ * the smaller of the two amounts still unmatched: the monotone
+ * (north-west-corner) coupling of the two sequences.  It is walked here
+ * with one cursor on each side; a source (target) whose amount is used up
+ * moves its cursor on, and a pair of cursors with no mass left on one side
+ * exchanges nothing, so the walk makes exactly the algorithm's nonzero
+ * matches, in its order and with its subtractions.  Entries with positive
+ * mass are written as (source bin i*n+j, target bin k*n+l, mass).  Returns
+ * the number of entries (which may exceed cap: then only the first cap
+ * entries are stored). */
 int64_t or_recover(int32_t m, int32_t n, const double *x, int64_t cap,
                    int32_t *src, int32_t *dst, double *mass) {
   int64_t N, M3;
   or_dims(m, n, &N, &M3);
-  double *f = (double *)malloc((size_t)N * sizeof(double));
-  for (int64_t e = 0; e < N; ++e) f[e] = x[e] > 0.0 ? x[e] : 0.0;
+  double *in = (double *)malloc((size_t)m * sizeof(double));   /* column of the bin */
+  double *out = (double *)malloc((size_t)n * sizeof(double));  /* row of the bin */
   int64_t nnz = 0;
   for (int32_t k = 0; k < m; ++k)
-    for (int32_t j = 0; j < n; ++j)
-      for (int32_t i = 0; i < m; ++i)
-        for (int32_t l = 0; l < n; ++l) {
-          double *a = &f[ix1(m, n, i, k, j)];
-          double *bb = &f[ix2(m, n, k, j, l)];
-          double pi = *a < *bb ? *a : *bb;
-          *a -= pi;
-          *bb -= pi;
-          if (pi > 0.0) {
-            if (nnz < cap) {
-              src[nnz] = i * n + j;
-              dst[nnz] = k * n + l;
-              mass[nnz] = pi;
-            }
-            ++nnz;
+    for (int32_t j = 0; j < n; ++j) {
+      for (int32_t i = 0; i < m; ++i) {
+        const double v = x[ix1(m, n, i, k, j)];
+        in[i] = v > 0.0 ? v : 0.0;
+      }
+      for (int32_t l = 0; l < n; ++l) {
+        const double v = x[ix2(m, n, k, j, l)];
+        out[l] = v > 0.0 ? v : 0.0;
+      }
+      int32_t i = 0, l = 0;
+      while (i < m && l < n) {
+        const double moved = in[i] < out[l] ? in[i] : out[l];
+        in[i] -= moved;
+        out[l] -= moved;
+        if (moved > 0.0) {
+          if (nnz < cap) {
+            src[nnz] = i * n + j;
+            dst[nnz] = k * n + l;
+            mass[nnz] = moved;
           }
+          ++nnz;
         }
-  free(f);
+        /* the side left with nothing moves on (both when both are used up) */
+        const int32_t adv_i = !(in[i] > 0.0), adv_l = !(out[l] > 0.0);
+        i += adv_i;
+        l += adv_l;
+      }
+    }
+  free(in);
+  free(out);
   return nnz;
 }
 
