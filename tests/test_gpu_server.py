@@ -146,3 +146,47 @@ def test_server_shared_slots_reused():
         alone, _ = c.solve(a, b, tol=1e-4, prec=hot.HOT_FP32_STREAM, max_iter=100000)
         for key in ("primal_obj", "kkt", "iters", "feaserr", "status"):
             assert got[t][key] == alone[key], (t, key)
+
+
+def test_server_shared_variants_equal_alone():
+    """Shared launches with the method's variants in one group: non-uniform
+    bins beside uniform ones, the ADMM baseline, absolute-KKT stopping and
+    fixed iterations; each result equals its solo hot_solve result."""
+    need_gpu()
+    from paper_2408_00598_amd import hot, workloads
+    c = ctx()
+    rng = np.random.default_rng(33)
+    R = hot.HOT_FLAG_RESTART
+    specs = [  # (m, n, prec, tol, flags, max_iter, non-uniform)
+        (40, 40, hot.HOT_FP64, 1e-6, R, 200000, True),
+        (44, 40, hot.HOT_FP64, 1e-6, R, 200000, False),
+        (48, 36, hot.HOT_FP64, 1e-5, hot.HOT_FLAG_ADMM, 200000, False),
+        (40, 48, hot.HOT_FP64, 1e-3, R | hot.HOT_FLAG_ABS_KKT, 200000, False),
+        (36, 44, hot.HOT_FP64, 1e-6, hot.HOT_FLAG_FIXED_ITERS, 300, False),
+        (42, 42, hot.HOT_FP64, 1e-6, R, 200000, True),
+    ]
+    reqs = []
+    for t, (m, n, prec, tol, flags, mi, nu) in enumerate(specs):
+        a = dev(workloads.gaussian_blobs(m, n, 2, rng))
+        b = dev(workloads.gaussian_blobs(m, n, 3, rng))
+        kw = dict(tol=tol, prec=prec, flags=flags, max_iter=mi)
+        if nu:
+            kw["coord_row"] = dev(workloads.grid_lines(m, rng))
+            kw["coord_col"] = dev(workloads.grid_lines(n, rng))
+        reqs.append((t, a, b, kw))
+    srv = hot.Server(c, max_slots=6, shared=True)
+    for q, (t, a, b, kw) in enumerate(reqs):
+        srv.submit(a, b, t, **kw)
+        if q == 2:
+            time.sleep(0.02)
+    assert srv.drain(300.0) == hot.HOT_OK
+    got = {r["tag"]: r for r in srv.poll(16)}
+    st = srv.stats()
+    srv.close()
+    assert len(got) == len(reqs) and st["max_shared"] >= 2
+    for t, a, b, kw in reqs:
+        alone, _ = c.solve(a, b, **kw)
+        r = got[t]
+        assert r["status"] == alone["status"] and r["status"] == hot.HOT_OK, (t, r["status"])
+        for key in ("primal_obj", "dual_obj", "kkt", "kkt_abs", "feaserr", "iters", "restarts"):
+            assert r[key] == alone[key], (t, key, r[key], alone[key])
