@@ -616,7 +616,6 @@ hot_status Workspace::setup_slot(hot_ctx* ctx, int s, const hot_problem& pr, con
 }
 
 hot_status Workspace::init_group(hot_ctx* ctx, hipStream_t st) {
-  (void)ctx;
   const size_t K = lay.geo.size();
   HIPCK(hipMemcpyAsync(geo_d, lay.geo.data(), K * sizeof(PairGeo), hipMemcpyHostToDevice, st));
   launch_zero(ctl_d, 2 * K * sizeof(PairCtl), st);
