@@ -267,6 +267,9 @@ hot_status validate_problem_public(hot_ctx* ctx, const hot_problem* p) {
 hot_status Workspace::setup(hot_ctx* ctx, const hot_problem* probs, int count, hipStream_t st) {
   const size_t np = lay.geo.size();
   escalated_at = 0;
+  prof_seconds = 0.0;  // (a cached workspace starts its counts afresh)
+  prof_launches = 0;
+  iterations_launched = 0;
   restore_tables();  // (no graph is in flight between runs)
   drop_retired();
   std::vector<const double*> ptrs(2 * np);
@@ -1102,6 +1105,7 @@ void Workspace::fill_result(int p, hot_result* r, double seconds) const {
 struct hot_batch {
   hot_ctx* ctx = nullptr;
   GroupedBatch gb;
+  std::string key;  // workspace-cache key of its shapes and grouping
   std::thread th;
   hot_status status = HOT_OK;
   double seconds = 0;
@@ -1311,6 +1315,55 @@ hot_status make_groups(hot_ctx* ctx, const hot_problem* probs, int count, int gr
   return HOT_OK;
 }
 
+// at most this many cached entries / bytes per context
+constexpr size_t kWsCacheEntries = 8;
+constexpr size_t kWsCacheBytes = size_t(8) << 30;
+
+std::string ws_cache_key(const hot_problem* probs, int count, int groups) {
+  std::string k = std::to_string(groups) + "/" + std::to_string(probs[0].prec);
+  for (int p = 0; p < count; ++p)
+    k += "/" + std::to_string(probs[p].m) + "x" + std::to_string(probs[p].n);
+  return k;
+}
+
+bool ws_cache_take(hot_ctx* ctx, const std::string& key, GroupedBatch& gb) {
+  if (ctx->profiling || ctx->nan_after >= 0) return false;
+  for (auto it = ctx->ws_cache.begin(); it != ctx->ws_cache.end(); ++it)
+    if (it->key == key) {
+      gb = std::move(it->gb);
+      ctx->ws_cache_bytes -= it->bytes;
+      ctx->ws_cache.erase(it);
+      return true;
+    }
+  return false;
+}
+
+void ws_cache_put(hot_ctx* ctx, const std::string& key, GroupedBatch&& gb) {
+  // (timed runs and failure-path tests build their own workspaces)
+  if (ctx->profiling || ctx->nan_after >= 0) return;
+  size_t bytes = 0;
+  for (const auto& ws : gb.wss) {
+    if (ws->profile || ws->arena) return;
+    bytes += ws->lay.bytes(ws->sbx ? HOT_FLAG_SIGMA_UPDATE : 0);
+  }
+  if (bytes > kWsCacheBytes) return;
+  hot_ctx::CachedWs e;
+  e.key = key;
+  e.gb = std::move(gb);
+  e.bytes = bytes;
+  ctx->ws_cache.push_front(std::move(e));
+  ctx->ws_cache_bytes += bytes;
+  while (ctx->ws_cache.size() > kWsCacheEntries || ctx->ws_cache_bytes > kWsCacheBytes) {
+    ctx->ws_cache_bytes -= ctx->ws_cache.back().bytes;
+    ctx->ws_cache.pop_back();
+  }
+}
+
+void ws_cache_clear(hot_ctx* ctx) {
+  ctx->ws_cache.clear();
+  ctx->ws_cache_bytes = 0;
+}
+
 // Iterate several workspaces (disjoint problems) concurrently, each on its
 // own stream with two captured graphs in flight, until all have stopped.
 hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Workspace>>& wss,
@@ -1422,8 +1475,16 @@ hot_status hot_solve(hot_ctx* ctx, const hot_problem* prob, hot_stream_t stream,
   if (hipSetDevice(ctx->device) != hipSuccess) return HOT_E_DEVICE;
   const auto t0 = std::chrono::steady_clock::now();
   std::shared_ptr<Workspace> ws;
-  hot_status s = make_workspace(ctx, prob, 1, ws);
+  hot_status s = validate_problem(ctx, prob);
   if (s != HOT_OK) return s;
+  const std::string key = ws_cache_key(prob, 1, 1);
+  GroupedBatch cached;
+  if (ws_cache_take(ctx, key, cached)) {
+    ws = cached.wss[0];
+  } else {
+    s = make_workspace(ctx, prob, 1, ws);
+    if (s != HOT_OK) return s;
+  }
   hipStream_t st = ws->stream;
   // order after the caller's stream
   hipEvent_t ev;
@@ -1443,6 +1504,13 @@ hot_status hot_solve(hot_ctx* ctx, const hot_problem* prob, hot_stream_t stream,
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   ws->fill_result(0, res, secs);
+  if (!sol_out && ws->lay.fp32 == (prob->prec == HOT_FP32_STREAM ? 1 : 0)) {
+    // kept for the next solve of this shape (not a widened one)
+    GroupedBatch keep;
+    keep.wss.push_back(ws);
+    keep.where.push_back({0, 0});
+    ws_cache_put(ctx, key, std::move(keep));
+  }
   if (sol_out) {
     hot_solution* so = new hot_solution();
     so->ws = ws;
@@ -1527,13 +1595,27 @@ hot_status hot_batch_submit(hot_ctx* ctx, const hot_problem* probs, int32_t coun
   if (!ctx || !probs || !out || count < 1) return HOT_E_INVALID;
   *out = nullptr;
   GroupedBatch gb;
+  std::string key;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return HOT_E_DEVICE;
     // timed (profiling) solves run the batch as one launch per pass, so each
     // timed slab pass is the whole batch's; otherwise concurrent groups
-    hot_status s = make_groups(ctx, probs, count, ctx->profiling ? 1 : ctx->tune.batch_groups, gb);
+    const int groups = ctx->profiling ? 1 : ctx->tune.batch_groups;
+    key = ws_cache_key(probs, count, groups);
+    hot_status s = HOT_OK;
+    if (ws_cache_take(ctx, key, gb)) {  // same shapes: validate the problems only
+      for (int p = 0; p < count && s == HOT_OK; ++p) {
+        s = validate_problem(ctx, &probs[p]);
+        if (s == HOT_OK && probs[p].prec != probs[0].prec) {
+          ctx->err = "all problems of a batch must use the same precision";
+          s = HOT_E_INVALID;
+        }
+      }
+    } else {
+      s = make_groups(ctx, probs, count, groups, gb);
+    }
     if (s != HOT_OK) return s;
     // order every group after the caller's stream
     hipEvent_t ev;
@@ -1554,6 +1636,7 @@ hot_status hot_batch_submit(hot_ctx* ctx, const hot_problem* probs, int32_t coun
   b->ctx = ctx;
   b->gb = std::move(gb);
   b->count = count;
+  b->key = key;
   const int64_t max_graphs = max_it * 2 / kGraphIters + 8;
   const int dev = ctx->device;
   b->th = std::thread([b, max_graphs, dev]() {
@@ -1580,6 +1663,10 @@ hot_status hot_batch_wait(hot_batch* b, hot_result* results) {
   if (s == HOT_OK && results)
     for (int p = 0; p < b->count; ++p)
       b->gb.wss[b->gb.where[p].first]->fill_result(b->gb.where[p].second, &results[p], b->seconds);
+  if (s == HOT_OK) {  // kept for the next batch of these shapes
+    std::lock_guard<std::mutex> lk(b->ctx->mu);
+    ws_cache_put(b->ctx, b->key, std::move(b->gb));
+  }
   delete b;
   return s;
 }

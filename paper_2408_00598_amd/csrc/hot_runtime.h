@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -262,6 +263,13 @@ hot_status make_groups(hot_ctx* ctx, const hot_problem* probs, int count, int gr
 hot_status run_concurrent(hot_ctx* ctx, const std::vector<std::shared_ptr<Workspace>>& wss,
                           int64_t max_graphs);
 
+// Workspace cache of a context (caller holds ctx->mu): the key of a call,
+// take a matching entry, keep a finished one, drop all.
+std::string ws_cache_key(const hot_problem* probs, int count, int groups);
+bool ws_cache_take(hot_ctx* ctx, const std::string& key, GroupedBatch& gb);
+void ws_cache_put(hot_ctx* ctx, const std::string& key, GroupedBatch&& gb);
+void ws_cache_clear(hot_ctx* ctx);
+
 }  // namespace hot
 
 struct hot_ctx {
@@ -282,6 +290,18 @@ struct hot_ctx {
   std::mutex rec_mu;
   void* rec_buf = nullptr;
   size_t rec_bytes = 0;
+  // Workspaces of finished solves and batches, kept for the next call with
+  // the same shapes, precision and grouping (most recent first; a few
+  // entries and a byte cap; cleared when the launch-shape tuning changes).
+  // A reused workspace is set up afresh (control blocks, state, tables);
+  // only its allocation and captured graph are saved.
+  struct CachedWs {
+    std::string key;
+    hot::GroupedBatch gb;
+    size_t bytes = 0;
+  };
+  std::list<CachedWs> ws_cache;
+  size_t ws_cache_bytes = 0;
   ~hot_ctx() {
     if (rec_buf) (void)hipFree(rec_buf);
   }

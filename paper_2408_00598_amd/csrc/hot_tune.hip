@@ -128,6 +128,7 @@ extern "C" hot_status hot_autotune(hot_ctx* ctx, const hot_problem* probs, int32
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tune.table[key] = bestc;
+    ws_cache_clear(ctx);  // (layouts follow the tuning)
   }
   if (cache_path && cache_path[0]) {
     FILE* f = std::fopen(cache_path, "a");
@@ -174,5 +175,9 @@ extern "C" hot_status hot_autotune_load(hot_ctx* ctx, const char* cache_path) {
     }
   }
   std::fclose(f);
+  if (loaded > 0) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ws_cache_clear(ctx);  // (layouts follow the tuning)
+  }
   return loaded > 0 ? HOT_OK : HOT_E_INVALID;
 }
