@@ -10,7 +10,11 @@
  * tests/test_oracle_*.py: a Kronecker-product construction of A from the
  * paper's definitions, a dense solve of A A^T y = R, a dense simplex cross-
  * checked against an independent LP solver, 1-D CDF closed forms, the
- * translation and separable closed forms, and Prop. 1 on LP-exact flows.
+ * translation and separable closed forms, Prop. 1 on LP-exact flows, the
+ * relative KKT residual (eq. kkt_res) and feasibility error recomputed with
+ * numpy, and the restart rule replayed from the per-check trace.  Iteration
+ * counts against the paper's tables are parity unpinned: its sigma and
+ * restart rules are not printed.
  */
 #include "hot_oracle.h"
 
