@@ -203,20 +203,32 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+# the slab kernels' source and the headers whose types and helpers they use
+SLAB_SOURCES = ("hot_slab.hip", "hot_internal.h", "hot_device.h")
+
+
+def slab_source_sha256(root=None):
+    """One SHA-256 over the slab kernels' source files, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SLAB_SOURCES:
+        h.update(f.encode() + b"\0")
+        h.update(open(os.path.join(root or ROOT, "paper_2408_00598_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, launch):
     """HBM traffic per slab-pass launch from the committed rocprofv3 counter
-    summary of this workload, if it was taken on the current kernel source
+    summary of this workload, if it was taken on the current kernel sources
     and launch shape."""
-    import hashlib
     name = {"batched": "slab_pass_batched256_fp32_traffic.md",
             "pair512": "slab_pass_pair512_fp32_traffic.md"}.get(workload)
     if not name:
         return None
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2408_00598_amd", "csrc", "hot_slab.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = slab_source_sha256()
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith(("#", "|", "`")):

@@ -61,8 +61,13 @@ def test_traffic_is_reported_only_for_the_profiled_source_and_launch(tmp_path, m
     b = _bench()
     src = tmp_path / "paper_2408_00598_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "hot_slab.hip").write_text("// kernel source v1\n")
-    sha = hashlib.sha256((src / "hot_slab.hip").read_bytes()).hexdigest()
+    for f in b.SLAB_SOURCES:
+        (src / f).write_text(f"// {f} v1\n")
+    sha = b.slab_source_sha256(str(tmp_path))
+    h = hashlib.sha256()  # the digest is over name and contents of each file in turn
+    for f in b.SLAB_SOURCES:
+        h.update(f.encode() + b"\0" + (src / f).read_bytes())
+    assert sha == h.hexdigest()
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "slab_pass_batched256_fp32_traffic.md").write_text(
@@ -73,6 +78,10 @@ def test_traffic_is_reported_only_for_the_profiled_source_and_launch(tmp_path, m
     assert b.measured_traffic("batched", launch) == pytest.approx(2.97)
     assert b.measured_traffic("batched", "item_elems=4096,unroll=2,vec_per_lane=2") is None
     assert b.measured_traffic("pair128", launch) is None  # no summary for that workload
+    (src / "hot_internal.h").write_text("// hot_internal.h v2\n")  # a struct it reads changed
+    assert b.measured_traffic("batched", launch) is None
+    (src / "hot_internal.h").write_text("// hot_internal.h v1\n")
+    assert b.measured_traffic("batched", launch) == pytest.approx(2.97)
     (src / "hot_slab.hip").write_text("// kernel source v2\n")  # the kernel changed
     assert b.measured_traffic("batched", launch) is None
 
