@@ -355,7 +355,7 @@ def main():
                          "hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     if args.workload == "serving":
