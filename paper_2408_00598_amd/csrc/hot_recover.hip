@@ -13,9 +13,10 @@
 //
 // A bin's inputs are one row of each family's slabs: row k of F1^(j)
 // (sources) and row j of F2^(k) (targets), both contiguous.  One wave takes a
-// bin at a time: lanes own sources (or targets) i = lane + 64 r, the running
-// totals come from a fixed-order wave scan per 64-element round (with a
-// running maximum, exact, so that they never decrease), and the side that is
+// bin at a time: lane t owns the contiguous block i = t B .. t B + B - 1 of a
+// row (B = ceil(L / 64)), the running totals are the sequential sums inside
+// the block plus a fixed-order wave scan of the block totals (with a running
+// maximum, exact, so that they never decrease), and the side that is
 // searched sits in the wave's LDS.  Three passes over the bins, each needing
 // the previous one's global result:
 //   rows:  raw matched amount of every source (clipped at the bin's target
@@ -501,9 +502,10 @@ __global__ __launch_bounds__(64 * kRecWaves) void k_rec_cols(RecArgs A,
 // Unit (j, g) as in pass 1.  Entries: the positive segments between
 // consecutive values of the merged source and target totals, in order; lane
 // t walks the merged positions [t S, (t+1) S) from a merge-path split (the
-// same work on every lane however the mass is spread), once to count and
-// once to write after a wave scan of the counts, so the bin's entries are
-// one contiguous run in walk order.  Row sums: per source, G(P_{i+1}) -
+// same work on every lane however the mass is spread) once, recording per
+// step whether it took a source total and whether it closed an entry; after
+// a wave scan of the entry counts the keys are emitted from those bits, so
+// the bin's entries are one contiguous run in walk order.  Row sums: per source, G(P_{i+1}) -
 // G(P_i) with G the cumulative column-scaled target amount, times R_i.
 template <typename T, int MAXB, bool UNI>
 __global__ __launch_bounds__(64 * kRecWaves) void k_rec_write(
