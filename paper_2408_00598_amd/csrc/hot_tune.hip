@@ -1,11 +1,13 @@
 // Autotuner of the slab-pass launch shape (hot_autotune, hot_autotune_load).
 //
-// For a set of problem shapes, every candidate workgroup size (elements per
-// slab-pass workgroup, 2^11 .. 2^17) and row unroll (1, 2) is timed on a fixed
-// number of iterations of uniform histograms with hipEvents around each slab
-// pass; the fastest is stored in the context for launches of that total size
-// and precision, and optionally appended to a JSON-lines cache file keyed by
-// device architecture, precision and size class.
+// For a set of problem shapes, the built-in rule and every candidate of
+// elements per slab-pass workgroup (2^11 .. 2^17) x row unroll (1, 2) x
+// 16-byte vectors per lane (2, 4) are timed on a fixed number of iterations
+// of uniform histograms: whole iterations (slab pass, reduce, solve) as the
+// solver runs them, a batch's groups on their own streams, captured graphs,
+// wall clock after the set-up.  The fastest is stored in the context for
+// launches of that precision, size class and pair-count class, and optionally
+// appended to a JSON-lines cache file keyed by device architecture.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
