@@ -175,7 +175,8 @@ hot_status hot_ctx_profile_read(hot_ctx *ctx, double *out);
 /* Autotuner of the slab-pass launch shape.  For the shapes and precision of
  * probs (histogram values are ignored: uniform histograms are solved),
  * times `iters` fixed iterations (slab pass, reduce and solve, in captured
- * graphs, hipEvents around the run), each pass streaming the state, a (zero)
+ * graphs, host wall clock around the run after the set-up has finished),
+ * each pass streaming the state, a (zero)
  * Halpern anchor and the new state as every pass after the first restart
  * does, under each candidate workgroup size (2^11 ..
  * 2^17 flow elements per workgroup), row unroll (1, 2) and 16-byte vectors
