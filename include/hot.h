@@ -247,8 +247,9 @@ hot_status hot_solution_anchor(hot_ctx *ctx, const hot_solution *sol,
  * hipMalloc).  Every device buffer of the solve is carved from one static
  * device array of hot_noalloc_capacity() bytes (64 MiB) that each device
  * holds until the process ends: a problem whose workspace does not fit
- * (e.g. above 128 x 128 with FP32 streams or 96 x 96 in FP64) is rejected with
- * HOT_E_INVALID and a message giving the bytes it needs.  The iteration runs
+ * (with the built-in launch rule, square grids above 136 x 136 with FP32
+ * streams or 110 x 110 in FP64) is rejected with HOT_E_INVALID and a
+ * message giving the bytes it needs.  The iteration runs
  * on `stream` by direct launches (no graph, no event, no pinned buffer); the
  * call returns when done.  Same kernels, launch shapes and order as
  * hot_solve, so `res` and the iterate are bit-identical to it (res->seconds
